@@ -1,0 +1,311 @@
+/*
+ * chebfd.h -- C ABI of the MI355X (gfx950) Chebyshev filter diagonalisation
+ * library.
+ *
+ * The library computes the eigenpairs (lambda_i, v_i) of a sparse Hermitian
+ * matrix H that lie in a target window [lam_lo, lam_hi], each with residual
+ * ||H v_i - lambda_i v_i|| <= eps (problem statement of Sec. 2 of Pieper et
+ * al., arXiv:1510.04895), by the ChebFD scheme of Sec. 3.1: a Chebyshev
+ * window-filter polynomial p(H) of degree N_p applied to a block of N_S search
+ * vectors (Fig. fig:ChebFD), followed by orthogonalisation, Rayleigh-Ritz and
+ * a residual check.
+ *
+ * Conventions for every entry point
+ *  - Return value: 0 = success; negative = error (nothing was written to the
+ *    outputs unless stated); positive = warning, outputs are valid.
+ *    chebfd_last_error() gives a message for the calling thread.
+ *  - Complex numbers are stored interleaved (re, im): "c128" = two doubles,
+ *    "c64" = two floats.
+ *  - Blocks of vectors are row-major: element (row i, column k) at
+ *    base[i * ld + k] (in complex elements), ld >= n_s.  Row i is the i-th
+ *    component of every search vector (Sec. 4: row-major block vectors).
+ *  - "device" pointers are HIP device memory owned by the caller; the library
+ *    never frees them.  "host" pointers are ordinary memory.
+ *  - Work is enqueued on the stream given to chebfd_create(); the low-level
+ *    calls return without synchronising unless stated.
+ *  - One context per host thread.  Handles (matrix, result) are owned by the
+ *    library until the matching *_destroy.
+ */
+#ifndef CHEBFD_H
+#define CHEBFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chebfd_ctx chebfd_ctx;
+typedef struct chebfd_matrix chebfd_matrix;
+typedef struct chebfd_result chebfd_result;
+
+/* status codes */
+#define CHEBFD_OK 0
+#define CHEBFD_ERR_INVALID_ARG (-1)
+#define CHEBFD_ERR_OOM (-2)
+#define CHEBFD_ERR_HIP (-3)
+#define CHEBFD_ERR_NONFINITE (-4)
+#define CHEBFD_ERR_UNSUPPORTED (-5)
+#define CHEBFD_ERR_WORKSPACE (-6)
+#define CHEBFD_WARN_NOT_CONVERGED 1
+#define CHEBFD_WARN_SEARCH_SPACE_TOO_SMALL 2
+
+/* damping kernels g_n (Table tab:Kernel) */
+#define CHEBFD_KERNEL_NONE 0
+#define CHEBFD_KERNEL_FEJER 1
+#define CHEBFD_KERNEL_JACKSON 2
+#define CHEBFD_KERNEL_LANCZOS 3
+
+/* arithmetic of the filter sweep */
+#define CHEBFD_PREC_C128 0   /* complex128 storage, FP64 recurrence */
+#define CHEBFD_PREC_C64 1    /* complex64 storage, FP32 recurrence */
+
+/* matrix storage */
+#define CHEBFD_STORAGE_SELL 0     /* SELL-C-sigma, values and column indices */
+#define CHEBFD_STORAGE_STENCIL 1  /* topological-insulator stencil, no index stream */
+
+/* ------------------------------------------------------------------ */
+/* context                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the null stream) on which all work is enqueued.  Fails with
+ * CHEBFD_ERR_HIP when no device is present. */
+int chebfd_create(chebfd_ctx **out, int device, void *hip_stream);
+int chebfd_destroy(chebfd_ctx *ctx);
+/* Blocks until all work enqueued by the context has finished. */
+int chebfd_synchronize(chebfd_ctx *ctx);
+const char *chebfd_strerror(int code);
+const char *chebfd_last_error(void);
+/* Library version string (host only). */
+const char *chebfd_version(void);
+
+/* ------------------------------------------------------------------ */
+/* sparse matrices                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Uploads a Hermitian matrix given in CSR (0-based; rowptr has n+1 int64
+ * entries, col int32, val n_nz interleaved complex doubles; host memory, only
+ * read) into SELL-C-sigma storage (Sec. 4.2): rows are sorted by length
+ * within windows of `sell_sigma` rows, grouped into chunks of `sell_C` rows
+ * and padded to the chunk's longest row.  Both a c128 and a c64 copy of the
+ * values are kept so either precision can run.  The Gershgorin interval of
+ * the rows (Sec. 3.1 step 1) is computed on the way.  Hermiticity is not
+ * checked.  Errors: INVALID_ARG (n < 1, sell_C not in {1,2,4,...,64},
+ * sell_sigma < 1 or not a multiple of sell_C, a column out of range, a
+ * decreasing rowptr), OOM. */
+int chebfd_matrix_from_csr(chebfd_ctx *ctx, int64_t n, const int64_t *rowptr,
+                           const int32_t *col, const double *val, int sell_C,
+                           int sell_sigma, chebfd_matrix **out);
+
+/* Builds the topological-insulator Hamiltonian of Sec. 5.1, Eq. (Ham), on an
+ * Lx x Ly x Lz lattice with 4 orbitals per site (N = 4 Lx Ly Lz):
+ *   site n = x + Lx (y + Ly z), row 4n + o, orbital o = 2 tau + s,
+ *   G0 = tau_z (x) s_0, Gj = tau_x (x) s_j,
+ *   on-site block m G0 + V_n 1,  V_n = V (u_n - 1/2),
+ *   H[n, n+e_j] = -t (G0 + i Gj)/2 and H[n+e_j, n] = -t (G0 - i Gj)/2,
+ * with u_n the counter-based uniform number of stream 0 at index n for
+ * `seed` (SplitMix64 finaliser; see chebfd_random_block).  Bit j of
+ * pbc_mask makes direction j periodic.  storage = SELL builds SELL-C-sigma
+ * (sell_C, sell_sigma as above); storage = STENCIL keeps only the per-site
+ * potential and generates the hopping blocks inside the kernel.
+ * Errors: INVALID_ARG (an extent < 1, N >= 2^31), OOM. */
+int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc_mask, double t,
+                     double m, double V, uint64_t seed, int storage, int sell_C,
+                     int sell_sigma, chebfd_matrix **out);
+
+/* Properties of a matrix handle (host outputs, any may be NULL):
+ * n rows, nnz stored entries without padding, padded entries, Gershgorin
+ * interval [g_lo, g_hi], and the bytes one filter step reads of the matrix
+ * in c128 and in c64 storage (0 for STENCIL). */
+int chebfd_matrix_info(const chebfd_matrix *H, int64_t *n, int64_t *nnz, int64_t *padded,
+                       double *g_lo, double *g_hi, int64_t *matrix_bytes_c128,
+                       int64_t *matrix_bytes_c64);
+int chebfd_matrix_destroy(chebfd_matrix *H);
+
+/* ------------------------------------------------------------------ */
+/* filter polynomials (host only)                                      */
+/* ------------------------------------------------------------------ */
+
+/* gamma_n = g_n c_n, n = 0..n_p (Sec. 2.1, Eqs. (W1)-(W2), Table
+ * tab:Kernel): c_n are the Chebyshev coefficients of the rectangular window
+ * on [lam_lo, lam_hi] in the spectral interval [a, b]
+ *   c_0 = (acos x_lo - acos x_hi)/pi,
+ *   c_n = 2/(pi n) (sin(n acos x_lo) - sin(n acos x_hi)),  x = alpha l + beta,
+ * (the sign the integral definition gives; arguments clamped to [-1,1]) and
+ * g_n the damping factors of `kernel` (Lanczos exponent `mu`; Jackson as
+ * printed, so g_{N_p-1} = g_{N_p} = 0).  `gamma_out` holds n_p + 1 doubles.
+ * Errors: INVALID_ARG (lam_lo >= lam_hi, a >= b, n_p < 2, unknown kernel,
+ * window not intersecting [a, b]). */
+int chebfd_coeffs(double lam_lo, double lam_hi, double a, double b, int n_p, int kernel,
+                  double mu, double *gamma_out);
+
+/* Damping factor sigma and quality eta = -n_p / log10(sigma) of a filter
+ * polynomial (Sec. 2.3): sigma = max |p| outside the search interval
+ * [s_lo, s_hi] over [a, b] divided by min |p| inside [t_lo, t_hi]. */
+int chebfd_filter_quality(const double *gamma, int n_p, double a, double b, double t_lo,
+                          double t_hi, double s_lo, double s_hi, double *sigma, double *eta);
+
+/* Polynomial degree minimising eta for the target window [t_lo, t_hi] and
+ * search interval [s_lo, s_hi] (Sec. 2.3, Sec. 3.1 step 3); searches
+ * n_p in [np_min, np_max] exhaustively (eta(n_p) has many local minima). */
+int chebfd_optimal_np(double a, double b, double t_lo, double t_hi, double s_lo, double s_hi,
+                      int kernel, double mu, int np_min, int np_max, int *n_p, double *eta);
+
+/* ------------------------------------------------------------------ */
+/* low-level device operations (caller-owned device buffers)           */
+/* ------------------------------------------------------------------ */
+
+/* The polynomial filter of Fig. fig:ChebFD, in place:
+ *   X <- p(H) X,  p(x) = sum_{n=0}^{n_p} gamma_n T_n(alpha x + beta),
+ *   alpha = 2/(b-a), beta = (a+b)/(a-b).
+ * gamma: host array of n_p + 1 doubles.  X, U, W: device blocks of n rows
+ * and n_s columns with leading dimension ld, element type per `precision`
+ * (c128 or c64); U and W are scratch and are overwritten.  The first step
+ * forms u = (alpha H + beta) x, w = 2 (alpha H + beta) u - x and
+ * x = gamma_0 x + gamma_1 u + gamma_2 w; every later step swaps u and w,
+ * forms w = 2 (alpha H + beta) u - w and adds gamma_n w to x, each step one
+ * fused kernel.  If moments_dev != NULL (device, (2 n_p + 1) x n_s doubles,
+ * row-major) it receives the Chebyshev moments mu_m = <x, T_m x> of the
+ * input columns, m = 0..2 n_p, obtained from mu_{2n} = 2<T_n x,T_n x> - mu_0
+ * and mu_{2n-1} = 2<T_{n-1} x,T_n x> - mu_1 (Sec. 4, moments during the
+ * filter).  Requirements: n_p >= 2, 1 <= n_s <= ld, a < b; for c64 ld and n_s
+ * even and the buffers 16-byte aligned.  Errors: INVALID_ARG, HIP. */
+int chebfd_filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                        const double *gamma, int n_p, double a, double b, void *X, void *U,
+                        void *W, int64_t n_s, int64_t ld, double *moments_dev);
+
+/* Y = (s_h H + s_u) X for a block (the plain spMMVM, Sec. 4), same layout
+ * rules as chebfd_filter_apply; X and Y must not overlap. */
+int chebfd_spmm(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, const void *X, void *Y,
+                int64_t n_s, int64_t ld, double s_h, double s_u);
+
+/* S = A^H B (n_a x n_b, complex128, row-major, device) for blocks A (n x n_a,
+ * lda) and B (n x n_b, ldb) of element type `precision`, accumulated in FP64
+ * on the matrix cores with a fixed-order split over rows (bitwise
+ * reproducible).  Errors: INVALID_ARG, HIP. */
+int chebfd_gram(chebfd_ctx *ctx, int precision, const void *A, int64_t lda, int64_t n_a,
+                const void *B, int64_t ldb, int64_t n_b, int64_t n, double *S_dev);
+
+/* C = A T (c_beta = 0) or C = C - A T (c_beta = 1) with A (n x k, lda,
+ * element type prec_a), T (k x m complex128 row-major, device) and C (n x m,
+ * ldc, element type prec_c); FP64 accumulation on the matrix cores.  C must
+ * not overlap A. */
+int chebfd_block_times(chebfd_ctx *ctx, int prec_a, const void *A, int64_t lda, int64_t n,
+                       int64_t k, const double *T_dev, int64_t m, int prec_c, void *C,
+                       int64_t ldc, int c_beta);
+
+/* res[j] = || HV_j - theta_j V_j ||_2 for j < m (FP64; V, HV n x m with ld;
+ * theta host, res host).  Synchronises. */
+int chebfd_residual_norms(chebfd_ctx *ctx, int precision, const void *V, const void *HV,
+                          int64_t n, int64_t m, int64_t ld, const double *theta, double *res);
+
+/* Fills columns [k0, k0 + m) of a block with counter-based random numbers:
+ * element (i, k) = (2u - 1) + i (2u' - 1), u = U(seed, stream, 2e),
+ * u' = U(seed, stream, 2e + 1), e = offset + i * n_s + k, where
+ * U(s, st, j) = (h >> 11) 2^-53, h = f(f(s + G (st + 1)) + G (j + 1)),
+ * G = 0x9E3779B97F4A7C15 and f is the SplitMix64 finaliser (Steele, Lea and
+ * Flood 2014).  Streams: 1 initial block, 3 refill. */
+int chebfd_random_block(chebfd_ctx *ctx, int precision, void *X, int64_t n, int64_t n_s,
+                        int64_t ld, int64_t k0, int64_t m, uint64_t seed, uint64_t stream,
+                        uint64_t offset);
+
+/* Converts a block between c128 and c64 (round to nearest). */
+int chebfd_convert(chebfd_ctx *ctx, int prec_in, const void *X, int prec_out, void *Y,
+                   int64_t n, int64_t n_s, int64_t ld_in, int64_t ld_out);
+
+/* Stochastic KPM moments of the density of states (Sec. 3.1 steps 1-2):
+ * mu_m = (1/(N R)) sum_r <x_r, T_m(alpha H + beta) x_r>, m = 0..n_mom-1,
+ * with R = n_vec random-phase vectors x_r (entries e^{2 pi i u}, u from
+ * stream 2), computed in `precision` with n_mom/2 fused steps (doubling).
+ * out: host, n_mom doubles.  a, b: spectral interval.  Synchronises. */
+int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, int n_vec,
+                       int n_mom, uint64_t seed, double a, double b, double *out);
+
+/* Launch configuration of the fused filter step for this context:
+ *   "lanes"       lanes sharing one row (SELL) or site (stencil): 16, 32, 64,
+ *                 0 = default (32; 16 for blocks of at most 16 packs);
+ *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
+ *   "order"       0 (default) = workgroups ordered column-slab major,
+ *                 1 = row-chunk major.
+ * Results are identical for every setting; only speed changes.
+ * Errors: INVALID_ARG for an unknown key or value. */
+int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value);
+
+/* Attainable HBM bandwidth (the read-only reduction benchmark of Sec. 4.1,
+ * plus a copy): reads `bytes` of the device buffer `buf` (caller-owned,
+ * 16-byte aligned, contents ignored, its second half overwritten by the
+ * copy) `reps` times.  Outputs GB/s (10^9 bytes/s).  Synchronises. */
+int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps,
+                           double *read_gbs, double *copy_gbs);
+
+/* Hermitian eigen-decomposition of a small dense matrix on the host
+ * (Householder tridiagonalisation + implicit QL): A (n x n complex128,
+ * row-major, host) is overwritten by the eigenvectors (columns), w receives
+ * the eigenvalues in ascending order. */
+int chebfd_host_eigh(int n, double *A, double *w);
+
+/* ------------------------------------------------------------------ */
+/* the ChebFD solver (Sec. 3.1 steps 1-8)                              */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double lam_lo, lam_hi;   /* target window I_T */
+    int n_s;                 /* search vectors N_S */
+    int n_p;                 /* filter degree N_p (>= 2) */
+    int kernel;              /* CHEBFD_KERNEL_* */
+    double mu;               /* Lanczos exponent */
+    double eps;              /* residual goal */
+    int max_iter;            /* outer iterations */
+    int precision;           /* CHEBFD_PREC_C128, or C64 (FP32 sweep + FP64 polish) */
+    int lock;                /* lock converged pairs (1) or not (0) */
+    double a, b;             /* spectral interval; NaN = Gershgorin of H */
+    uint64_t seed;           /* initial block: stream 1 of this seed */
+    const double *gamma_corr; /* NULL or host array of n_p + 1 multiplicative
+                                 corrections: gamma_n <- gamma_n (1 + corr_n) */
+    double polish_switch;    /* C64 only: go to FP64 once every in-window
+                                residual is below this or stops improving */
+    int vectors;             /* 1: copy the eigenvectors to the host result */
+} chebfd_params;
+
+typedef struct {
+    int iterations;          /* outer iterations (all phases) */
+    int iterations_c64;      /* of which in the FP32 sweep */
+    int n_found;
+    int n_locked;
+    int refilled;            /* random columns added by orthogonalisation */
+    int64_t n_mvm;           /* sum over iterations of active columns * n_p */
+    double a, b;
+    double t_total, t_filter, t_ortho, t_rr;   /* seconds */
+    double max_residual;
+} chebfd_stats;
+
+/* Fills `p` with defaults: Lanczos kernel mu = 2, eps 1e-9, max_iter 50, C128,
+ * lock 1, a = b = NaN, seed 1, polish_switch 1e-6, vectors 1, n_s 32,
+ * n_p 200. */
+int chebfd_params_default(chebfd_params *p);
+
+/* Device workspace (bytes) chebfd_solve needs for this matrix and params. */
+int chebfd_solve_workspace_size(const chebfd_matrix *H, const chebfd_params *p, int64_t *bytes);
+
+/* Runs the ChebFD scheme on H with a caller-provided device workspace of at
+ * least chebfd_solve_workspace_size bytes (256-byte aligned).  Converged
+ * in-window pairs (residual <= eps on H in FP64) are returned in a result
+ * handle, ascending in lambda.  Returns 0, NOT_CONVERGED (max_iter reached;
+ * the pairs converged so far are returned), SEARCH_SPACE_TOO_SMALL (every
+ * search vector ended up converged in the window, so the window may hold
+ * more), or an error (INVALID_ARG, WORKSPACE, HIP, NONFINITE). */
+int chebfd_solve(chebfd_ctx *ctx, const chebfd_matrix *H, const chebfd_params *p,
+                 void *workspace, int64_t workspace_bytes, chebfd_result **out);
+
+/* Pointers into the result (host memory owned by the result): n_found
+ * eigenvalues, residuals, and eigenvectors as an N x n_found row-major c128
+ * block.  Any output may be NULL. */
+int chebfd_result_get(const chebfd_result *r, int64_t *n_found, const double **evals,
+                      const double **residuals, const double **evecs, chebfd_stats *stats);
+int chebfd_result_destroy(chebfd_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

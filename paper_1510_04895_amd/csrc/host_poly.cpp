@@ -1,0 +1,171 @@
+// Host-side filter polynomial math (Sec. 2.1 and 2.3): window expansion
+// coefficients, damping kernels, Clenshaw evaluation, filter quality and the
+// eta-minimising polynomial degree.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+namespace chebfd {
+
+// c_n of the rectangular window W = 1 on [lo, hi] within [a, b] (Eq. (W1)).
+// With x = cos(theta) the integral (2 - d_n0)/pi int W T_n (1-x^2)^{-1/2} dx
+// becomes (2 - d_n0)/pi int_{theta_hi}^{theta_lo} cos(n theta) dtheta.
+void window_coeffs(double lo, double hi, double a, double b, int n_p, double *c)
+{
+    const double alpha = 2.0 / (b - a), beta = (a + b) / (a - b);
+    const double xl = std::min(1.0, std::max(-1.0, alpha * lo + beta));
+    const double xh = std::min(1.0, std::max(-1.0, alpha * hi + beta));
+    const double tl = std::acos(xl), th = std::acos(xh);
+    c[0] = (tl - th) / M_PI;
+    for (int n = 1; n <= n_p; ++n) c[n] = 2.0 * (std::sin(n * tl) - std::sin(n * th)) / (M_PI * n);
+}
+
+// Damping factors of Table tab:Kernel.
+void damping(int kernel, int n_p, double mu, double *g)
+{
+    const double np = (double)n_p;
+    for (int n = 0; n <= n_p; ++n) {
+        switch (kernel) {
+        case CHEBFD_KERNEL_FEJER:
+            g[n] = (np - n + 1.0) / (np + 1.0);
+            break;
+        case CHEBFD_KERNEL_JACKSON: {
+            const double q = M_PI / np;
+            g[n] = ((np - n) * std::cos(q * n) + std::sin(q * n) / std::tan(q)) / np;
+            break;
+        }
+        case CHEBFD_KERNEL_LANCZOS: {
+            if (n == 0) {
+                g[n] = 1.0;
+            } else {
+                const double s = M_PI * n / (np + 1.0);
+                g[n] = std::pow(std::sin(s) / s, mu);
+            }
+            break;
+        }
+        default:
+            g[n] = 1.0;
+        }
+    }
+}
+
+// p(x) = sum_n gamma_n T_n(alpha x + beta) by Clenshaw's backward recurrence.
+double poly_value(const double *gamma, int n_p, double a, double b, double x)
+{
+    const double y = (2.0 * x - a - b) / (b - a);
+    double b1 = 0.0, b2 = 0.0;
+    for (int n = n_p; n >= 1; --n) {
+        const double t = gamma[n] + 2.0 * y * b1 - b2;
+        b2 = b1;
+        b1 = t;
+    }
+    return gamma[0] + y * b1 - b2;
+}
+
+// sigma = max_{x in [a,b] \ [s_lo,s_hi]} |p| / min_{x in [t_lo,t_hi]} |p|,
+// eta = -n_p / log10 sigma (Sec. 2.3).  |p| is sampled on a grid uniform in
+// theta = acos((2x - a - b)/(b - a)) with 8 points per period of T_{n_p},
+// plus the four interval edges.
+void quality(const double *gamma, int n_p, double a, double b, double t_lo, double t_hi,
+             double s_lo, double s_hi, double *sigma, double *eta)
+{
+    const int M = std::max(8 * (n_p + 1) / 2, 64);
+    double mx = 0.0, mn = INFINITY;
+    for (int k = 0; k <= M; ++k) {
+        const double th = M_PI * k / M;
+        const double x = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(th);
+        const bool in_t = x >= t_lo && x <= t_hi;
+        const bool out_s = x < s_lo || x > s_hi;
+        if (!in_t && !out_s) continue;
+        const double p = std::fabs(poly_value(gamma, n_p, a, b, x));
+        if (in_t) mn = std::min(mn, p);
+        if (out_s) mx = std::max(mx, p);
+    }
+    for (double x : {t_lo, t_hi}) mn = std::min(mn, std::fabs(poly_value(gamma, n_p, a, b, x)));
+    for (double x : {s_lo, s_hi}) mx = std::max(mx, std::fabs(poly_value(gamma, n_p, a, b, x)));
+    *sigma = mx / mn;
+    *eta = (*sigma < 1.0) ? -n_p / std::log10(*sigma) : INFINITY;
+}
+
+}  // namespace chebfd
+
+using namespace chebfd;
+
+extern "C" int chebfd_coeffs(double lam_lo, double lam_hi, double a, double b, int n_p,
+                             int kernel, double mu, double *gamma_out)
+{
+    if (!gamma_out) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_coeffs: gamma_out is NULL");
+    if (!(lam_lo < lam_hi) || !(a < b) || n_p < 2 || kernel < 0 || kernel > 3 ||
+        !std::isfinite(lam_lo) || !std::isfinite(lam_hi))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_coeffs: need lam_lo < lam_hi, a < b, n_p >= 2, kernel 0..3");
+    if (lam_hi <= a || lam_lo >= b)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_coeffs: window does not intersect [a, b]");
+    std::vector<double> g(n_p + 1);
+    window_coeffs(lam_lo, lam_hi, a, b, n_p, gamma_out);
+    damping(kernel, n_p, mu, g.data());
+    for (int n = 0; n <= n_p; ++n) gamma_out[n] *= g[n];
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_filter_quality(const double *gamma, int n_p, double a, double b,
+                                     double t_lo, double t_hi, double s_lo, double s_hi,
+                                     double *sigma, double *eta)
+{
+    if (!gamma || !sigma || !eta || n_p < 1 || !(a < b) || !(t_lo < t_hi) || s_lo > t_lo ||
+        s_hi < t_hi)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_filter_quality: invalid arguments");
+    quality(gamma, n_p, a, b, t_lo, t_hi, s_lo, s_hi, sigma, eta);
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_optimal_np(double a, double b, double t_lo, double t_hi, double s_lo,
+                                 double s_hi, int kernel, double mu, int np_min, int np_max,
+                                 int *n_p, double *eta_out)
+{
+    if (!n_p || !eta_out || np_min < 2 || np_max < np_min || !(a < b) || !(t_lo < t_hi) ||
+        s_lo > t_lo || s_hi < t_hi)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_optimal_np: invalid arguments");
+    std::map<int, double> f;
+    std::vector<double> gam, g;
+    auto ev = [&](int k) {
+        auto it = f.find(k);
+        if (it != f.end()) return it->second;
+        gam.resize(k + 1);
+        g.resize(k + 1);
+        window_coeffs(t_lo, t_hi, a, b, k, gam.data());
+        damping(kernel, k, mu, g.data());
+        for (int n = 0; n <= k; ++n) gam[n] *= g[n];
+        double s, e;
+        quality(gam.data(), k, a, b, t_lo, t_hi, s_lo, s_hi, &s, &e);
+        f[k] = e;
+        return e;
+    };
+    // eta(n_p) is jagged: scan a 0.5% geometric grid, then every integer
+    // within +-2% of the three best grid points.
+    std::vector<int> grid;
+    for (double x = np_min; x <= np_max * 1.0000001; x *= 1.005) {
+        const int k = (int)std::lround(x);
+        if (grid.empty() || grid.back() != k) grid.push_back(k);
+    }
+    if (grid.back() != np_max) grid.push_back(np_max);
+    std::vector<std::pair<double, int>> sc;
+    for (int k : grid) sc.push_back({ev(k), k});
+    std::sort(sc.begin(), sc.end());
+    for (size_t i = 0; i < std::min<size_t>(3, sc.size()); ++i) {
+        const int k = sc[i].second, w = std::max(2, (int)(0.02 * k));
+        for (int j = std::max(np_min, k - w); j <= std::min(np_max, k + w); ++j) ev(j);
+    }
+    int best = np_min;
+    double be = INFINITY;
+    for (auto &kv : f)
+        if (kv.second < be) {
+            be = kv.second;
+            best = kv.first;
+        }
+    *n_p = best;
+    *eta_out = be;
+    return CHEBFD_OK;
+}

@@ -1,0 +1,154 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chebfd.h"
+
+namespace chebfd {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define CHEBFD_HIP(call)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::chebfd::fail(CHEBFD_ERR_HIP, std::string(#call ": ") +            \
+                                                      hipGetErrorString(e_));         \
+    } while (0)
+
+#define CHEBFD_CHECK_LAUNCH()                                                         \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess)                                                         \
+            return ::chebfd::fail(CHEBFD_ERR_HIP, std::string("kernel launch: ") +     \
+                                                      hipGetErrorString(e_));         \
+    } while (0)
+
+// ---------------------------------------------------------------- handles
+struct Sell {
+    int64_t n = 0;           // rows
+    int C = 32;              // chunk height
+    int sigma = 256;         // sorting window
+    int64_t nchunks = 0;
+    int64_t nnz = 0;         // stored entries without padding
+    int64_t stored = 0;      // stored entries with padding
+    int max_len = 0;         // longest row
+    // device arrays
+    int64_t *chunk_ptr = nullptr;   // nchunks + 1, offset of chunk c's first slot
+    int32_t *chunk_len = nullptr;   // nchunks, padded width of chunk c
+    int32_t *perm = nullptr;        // nchunks*C: original row of slot (or -1)
+    int32_t *col = nullptr;         // stored
+    double *val64 = nullptr;        // stored complex128 (interleaved)
+    float *val32 = nullptr;         // stored complex64
+};
+
+struct Stencil {
+    int L[3] = {0, 0, 0};
+    int pbc = 0;
+    double t = 1.0, m = 2.0;
+    double *pot64 = nullptr;  // per-site potential V_n (device)
+    float *pot32 = nullptr;
+};
+
+}  // namespace chebfd
+
+struct chebfd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // persistent small device scratch (partial sums, small matrices)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    double *pinned = nullptr;       // host pinned staging for small results
+    size_t pinned_bytes = 0;
+    int num_cu = 256;
+    // launch configuration of the fused step (chebfd_set_tuning)
+    int tune_lpr = 0;     // lanes per row/site: 0 = default (32), 16, 32, 64
+    int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
+    int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
+};
+
+struct chebfd_matrix {
+    int storage = CHEBFD_STORAGE_SELL;
+    int64_t n = 0;
+    double g_lo = 0.0, g_hi = 0.0;  // Gershgorin interval
+    chebfd::Sell sell;
+    chebfd::Stencil st;
+    int device = 0;
+};
+
+namespace chebfd {
+
+// scratch management (grows on demand; synchronises the stream before growing)
+int ensure_scratch(chebfd_ctx *ctx, size_t bytes);
+int ensure_pinned(chebfd_ctx *ctx, size_t bytes);
+
+// ---------------------------------------------------------------- kernels
+// Step modes of the fused kernel.
+enum StepMode { MODE_APPLY = 0, MODE_SECOND = 1, MODE_STEP = 2 };
+
+struct StepArgs {
+    int mode;
+    int precision;
+    const void *u;     // gathered block
+    const void *wold;  // subtracted block (MODE_SECOND: x, MODE_STEP: w)
+    void *wout;        // written block
+    void *y;           // accumulated block (MODE_SECOND: x, MODE_STEP: x)
+    int64_t n, n_s, ld;
+    double s_h, s_u;   // w = s_h H u + s_u u (- wold)
+    double g0, g1, g2; // MODE_SECOND: y = g0 x + g1 u + g2 w; MODE_STEP: y += g0 w
+    double *partials;  // moment partial sums, or nullptr
+};
+
+// Launches one fused step; returns number of partial-sum rows written
+// (per column triples) in *n_part when partials != nullptr.
+int launch_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a, int64_t *n_part);
+
+// Sums the moment partials of one step into the moment array.
+int launch_moment_finalize(chebfd_ctx *ctx, const double *partials, int64_t n_part,
+                           int64_t n_s, int mode, int step, double *mom);
+
+int launch_gram(chebfd_ctx *ctx, int prec, const void *A, int64_t lda, int64_t n_a,
+                const void *B, int64_t ldb, int64_t n_b, int64_t n, double *S_dev);
+int launch_block_times(chebfd_ctx *ctx, int prec_a, const void *A, int64_t lda, int64_t n,
+                       int64_t k, const double *T_dev, int64_t m, int prec_c, void *C,
+                       int64_t ldc, int c_beta);
+int launch_residuals(chebfd_ctx *ctx, int prec, const void *V, const void *HV, int64_t n,
+                     int64_t m, int64_t ld, const double *theta_dev, double *res_dev);
+int launch_random(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s, int64_t ld,
+                  int64_t k0, int64_t m, uint64_t seed, uint64_t stream, uint64_t offset);
+int launch_convert(chebfd_ctx *ctx, int prec_in, const void *X, int prec_out, void *Y,
+                   int64_t n, int64_t n_s, int64_t ld_in, int64_t ld_out);
+int launch_phase_block(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s,
+                       int64_t ld, uint64_t seed, uint64_t stream);
+int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps,
+                           double *read_gbs, double *copy_gbs);
+int launch_expand_T(chebfd_ctx *ctx, const double *T, int64_t k, int64_t m, double *Tr);
+int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, void *dst,
+                       int64_t ldd, int64_t d0, const int32_t *idx_dev, int64_t n, int64_t m);
+int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
+                 double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
+                 double *mom);
+int check_block(const char *who, int precision, const void *p, int64_t n, int64_t n_s,
+                int64_t ld, bool packed);
+
+// ---------------------------------------------------------------- host math
+void window_coeffs(double lo, double hi, double a, double b, int n_p, double *c);
+void damping(int kernel, int n_p, double mu, double *g);
+double poly_value(const double *gamma, int n_p, double a, double b, double x);
+void quality(const double *gamma, int n_p, double a, double b, double t_lo, double t_hi,
+             double s_lo, double s_hi, double *sigma, double *eta);
+int herm_eig(int n, std::vector<double> &A /* 2*n*n, overwritten by vectors */,
+             std::vector<double> &w);
+
+// host-side random numbers (same definition as the device kernels)
+uint64_t mix64(uint64_t z);
+double u01(uint64_t seed, uint64_t stream, uint64_t index);
+
+}  // namespace chebfd

@@ -1,0 +1,326 @@
+// Fused Chebyshev filter step for the topological-insulator Hamiltonian of
+// Sec. 5.1, Eq. (Ham), generated inside the kernel (the matrix is never
+// stored; only the per-site potential V_n is read).  Same three modes as the
+// SELL kernel.  A lane owns one lattice site (its four orbital rows) and NB
+// consecutive complex columns: it reads the four rows of the site and of its
+// six neighbours (28 packs for 4 output rows instead of 13 per row with an
+// index stream) and writes the four output rows.
+//
+// Hopping blocks, orbital o = 2 tau + s, G0 = tau_z s_0, Gj = tau_x s_j:
+//   H[n, n + e_j] = -t/2 (G0 + i Gj),  H[n, n - e_j] = -t/2 (G0 - i Gj),
+// so the contribution of neighbour n + d e_j (d = +-1) to row o is
+//   -t/2 ( G0[o][o] u[o] + d i Gj[o][o'] u[o'] ),
+// with o' the single orbital coupled by Gj: tau flipped, and s flipped for
+// j = x, y (s_x = 1, s_y = -i/+i) or kept for j = z (s_z = +1/-1).
+#include <type_traits>
+
+#include "internal.h"
+#include "pack.h"
+
+namespace chebfd {
+namespace {
+
+template <typename T, int NB>
+struct Site {
+    Pack<T, NB> o[4];
+};
+
+template <typename T, int NB>
+__device__ __forceinline__ Site<T, NB> load_site(const T *u, int64_t site, int64_t ld,
+                                                 int64_t c0, int cnt)
+{
+    Site<T, NB> s;
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+        s.o[o] = load_pack_n<T, NB>(u + 2 * ((4 * site + o) * ld + c0), cnt);
+    return s;
+}
+
+// acc[o] += th * (g0(o) un[o] + d * i * Gj[o][o'] un[o'])   (th = -t/2)
+template <typename T, int NB, int J>
+__device__ __forceinline__ void add_hop(Pack<T, NB> (&acc)[4], const Site<T, NB> &un, T th,
+                                        T d)
+{
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const T g0 = (o < 2) ? T(1) : T(-1);
+        const int tau = o >> 1, s = o & 1;
+        const int op = ((1 - tau) << 1) | (J == 2 ? s : 1 - s);
+        // c = d * i * Gj[o][o'] as (cr, ci)
+        T cr, ci;
+        if (J == 0) {            // s_x entry 1
+            cr = T(0);
+            ci = d;
+        } else if (J == 1) {     // s_y entry -i (s=0) or +i (s=1): d*i*(-+i) = +-d
+            cr = (s == 0) ? d : -d;
+            ci = T(0);
+        } else {                 // s_z entry +1 (s=0) or -1 (s=1)
+            cr = T(0);
+            ci = (s == 0) ? d : -d;
+        }
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            const T vr = g0 * un.o[o].re[e] + cr * un.o[op].re[e] - ci * un.o[op].im[e];
+            const T vi = g0 * un.o[o].im[e] + cr * un.o[op].im[e] + ci * un.o[op].re[e];
+            acc[o].re[e] += th * vr;
+            acc[o].im[e] += th * vi;
+        }
+    }
+}
+
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
+__global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc, T th, T mm,
+                                                 const T *__restrict__ pot, int64_t nsites,
+                                                 int64_t nblk, const T *__restrict__ u,
+                                                 const T *wold, T *wout, T *y, int64_t n_s,
+                                                 int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
+                                                 double *__restrict__ partials, int order,
+                                                 int64_t nslab)
+{
+    constexpr int SPW = 64 / LPS;   // sites per wave
+    constexpr int SPB = 4 * SPW;    // sites per workgroup
+    constexpr int SW = LPS * NB;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ssub = lane / LPS, cl = lane % LPS;
+    const int64_t b = blockIdx.x;
+    int64_t slab, sb;
+    if (order == 0) {
+        slab = b / nblk;
+        sb = b - slab * nblk;
+    } else {
+        sb = b / nslab;
+        slab = b - sb * nslab;
+    }
+    const int64_t c0 = slab * SW + (int64_t)cl * NB;
+    const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);
+    const int64_t site = sb * SPB + wave * SPW + ssub;
+    const bool active = c0 < n_s && site < nsites;
+
+    double m0[NB], m1[NB], m2[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
+
+    if (active) {
+        const int64_t lxy = (int64_t)Lx * Ly;
+        const int z = (int)(site / lxy);
+        const int64_t rem = site - (int64_t)z * lxy;
+        const int yy = (int)(rem / Lx);
+        const int x = (int)(rem - (int64_t)yy * Lx);
+        const Site<T, NB> uo = load_site<T, NB>(u, site, ld, c0, cnt);
+        const T vn = pot[site];
+        Pack<T, NB> acc[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const T d = ((o < 2) ? mm : -mm) + vn;
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                acc[o].re[e] = d * uo.o[o].re[e];
+                acc[o].im[e] = d * uo.o[o].im[e];
+            }
+        }
+        // +-x
+        {
+            int xp = x + 1, xm = x - 1;
+            const bool per = pbc & 1;
+            if (xp < Lx || per) {
+                if (xp >= Lx) xp -= Lx;
+                add_hop<T, NB, 0>(acc, load_site<T, NB>(u, site - x + xp, ld, c0, cnt), th, T(1));
+            }
+            if (xm >= 0 || per) {
+                if (xm < 0) xm += Lx;
+                add_hop<T, NB, 0>(acc, load_site<T, NB>(u, site - x + xm, ld, c0, cnt), th, T(-1));
+            }
+        }
+        // +-y
+        {
+            int yp = yy + 1, ym = yy - 1;
+            const bool per = (pbc >> 1) & 1;
+            if (yp < Ly || per) {
+                if (yp >= Ly) yp -= Ly;
+                add_hop<T, NB, 1>(acc, load_site<T, NB>(u, site + (int64_t)(yp - yy) * Lx, ld, c0, cnt),
+                                  th, T(1));
+            }
+            if (ym >= 0 || per) {
+                if (ym < 0) ym += Ly;
+                add_hop<T, NB, 1>(acc, load_site<T, NB>(u, site + (int64_t)(ym - yy) * Lx, ld, c0, cnt),
+                                  th, T(-1));
+            }
+        }
+        // +-z
+        {
+            int zp = z + 1, zm = z - 1;
+            const bool per = (pbc >> 2) & 1;
+            if (zp < Lz || per) {
+                if (zp >= Lz) zp -= Lz;
+                add_hop<T, NB, 2>(acc, load_site<T, NB>(u, site + (int64_t)(zp - z) * lxy, ld, c0, cnt),
+                                  th, T(1));
+            }
+            if (zm >= 0 || per) {
+                if (zm < 0) zm += Lz;
+                add_hop<T, NB, 2>(acc, load_site<T, NB>(u, site + (int64_t)(zm - z) * lxy, ld, c0, cnt),
+                                  th, T(-1));
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int64_t off = 2 * ((4 * site + o) * ld + c0);
+            Pack<T, NB> w;
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                w.re[e] = s_h * acc[o].re[e] + s_u * uo.o[o].re[e];
+                w.im[e] = s_h * acc[o].im[e] + s_u * uo.o[o].im[e];
+            }
+            if (MODE == MODE_APPLY) {
+                store_pack_n<T, NB, NT>(wout + off, w, cnt);
+                if (MOM) {
+#pragma unroll
+                    for (int e = 0; e < NB; ++e) {
+                        const double xr = uo.o[o].re[e], xi = uo.o[o].im[e];
+                        const double wr = w.re[e], wi = w.im[e];
+                        m0[e] += xr * xr + xi * xi;
+                        m1[e] += xr * wr + xi * wi;
+                        m2[e] += wr * wr + wi * wi;
+                    }
+                }
+            } else if (MODE == MODE_SECOND) {
+                const Pack<T, NB> xo = load_pack_n<T, NB, NT>(wold + off, cnt);
+                Pack<T, NB> xn;
+#pragma unroll
+                for (int e = 0; e < NB; ++e) {
+                    w.re[e] -= xo.re[e];
+                    w.im[e] -= xo.im[e];
+                    xn.re[e] = g0 * xo.re[e] + g1 * uo.o[o].re[e] + g2 * w.re[e];
+                    xn.im[e] = g0 * xo.im[e] + g1 * uo.o[o].im[e] + g2 * w.im[e];
+                }
+                store_pack_n<T, NB, NT>(wout + off, w, cnt);
+                store_pack_n<T, NB, NT>(y + off, xn, cnt);
+                if (MOM) {
+#pragma unroll
+                    for (int e = 0; e < NB; ++e) {
+                        m1[e] += (double)uo.o[o].re[e] * w.re[e] + (double)uo.o[o].im[e] * w.im[e];
+                        m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
+                    }
+                }
+            } else {
+                const Pack<T, NB> wo = load_pack_n<T, NB, NT>(wold + off, cnt);
+                Pack<T, NB> yv = load_pack_n<T, NB, NT>(y + off, cnt);
+#pragma unroll
+                for (int e = 0; e < NB; ++e) {
+                    w.re[e] -= wo.re[e];
+                    w.im[e] -= wo.im[e];
+                    yv.re[e] += g0 * w.re[e];
+                    yv.im[e] += g0 * w.im[e];
+                }
+                store_pack_n<T, NB, NT>(wout + off, w, cnt);
+                store_pack_n<T, NB, NT>(y + off, yv, cnt);
+                if (MOM) {
+#pragma unroll
+                    for (int e = 0; e < NB; ++e) {
+                        m1[e] += (double)uo.o[o].re[e] * w.re[e] + (double)uo.o[o].im[e] * w.im[e];
+                        m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
+                    }
+                }
+            }
+        }
+    }
+
+    if (MOM) {
+        __shared__ double red[4][64][3 * NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            for (int off = LPS; off < 64; off <<= 1) {
+                m0[e] += __shfl_xor(m0[e], off);
+                m1[e] += __shfl_xor(m1[e], off);
+                m2[e] += __shfl_xor(m2[e], off);
+            }
+            red[wave][lane][3 * e + 0] = m0[e];
+            red[wave][lane][3 * e + 1] = m1[e];
+            red[wave][lane][3 * e + 2] = m2[e];
+        }
+        __syncthreads();
+        if (wave == 0 && lane < LPS && c0 < n_s) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                if (e >= cnt) break;
+                double s[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    s[q] = red[0][lane][3 * e + q] + red[1][lane][3 * e + q] +
+                           red[2][lane][3 * e + q] + red[3][lane][3 * e + q];
+                double *p = partials + 3 * (sb * n_s + c0 + e);
+                p[0] = s[0];
+                p[1] = s[1];
+                p[2] = s[2];
+            }
+        }
+    }
+}
+
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
+int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
+{
+    constexpr int SPB = 4 * (64 / LPS);
+    constexpr int SW = LPS * NB;
+    const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
+    const int64_t nblk = (nsites + SPB - 1) / SPB;
+    const int64_t nslab = (a.n_s + SW - 1) / SW;
+    if (n_part) *n_part = nblk;
+    const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
+    hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
+                       dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,
+                       (T)(-0.5 * S.t), (T)S.m, pot, nsites, nblk, (const T *)a.u,
+                       (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld, (T)a.s_h,
+                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, ctx->tune_order, nslab);
+    CHEBFD_CHECK_LAUNCH();
+    return CHEBFD_OK;
+}
+
+template <typename T, int LPS, int NB, bool NT>
+int launch_ti_mode(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
+{
+    const bool mom = a.partials != nullptr;
+    switch (a.mode) {
+    case MODE_APPLY:
+        return mom ? launch_ti_t<T, LPS, NB, MODE_APPLY, true, NT>(ctx, S, a, n_part)
+                   : launch_ti_t<T, LPS, NB, MODE_APPLY, false, NT>(ctx, S, a, n_part);
+    case MODE_SECOND:
+        return mom ? launch_ti_t<T, LPS, NB, MODE_SECOND, true, NT>(ctx, S, a, n_part)
+                   : launch_ti_t<T, LPS, NB, MODE_SECOND, false, NT>(ctx, S, a, n_part);
+    default:
+        return mom ? launch_ti_t<T, LPS, NB, MODE_STEP, true, NT>(ctx, S, a, n_part)
+                   : launch_ti_t<T, LPS, NB, MODE_STEP, false, NT>(ctx, S, a, n_part);
+    }
+}
+
+template <typename T, int NB>
+int launch_ti_lps(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part, int lps)
+{
+    const bool nt = ctx->tune_nt != 0;
+    switch (lps) {
+    case 16:
+        return nt ? launch_ti_mode<T, 16, NB, true>(ctx, S, a, n_part)
+                  : launch_ti_mode<T, 16, NB, false>(ctx, S, a, n_part);
+    case 64:
+        return nt ? launch_ti_mode<T, 64, NB, true>(ctx, S, a, n_part)
+                  : launch_ti_mode<T, 64, NB, false>(ctx, S, a, n_part);
+    default:
+        return nt ? launch_ti_mode<T, 32, NB, true>(ctx, S, a, n_part)
+                  : launch_ti_mode<T, 32, NB, false>(ctx, S, a, n_part);
+    }
+}
+
+}  // namespace
+
+int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb);
+
+int launch_stencil_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a,
+                        int64_t *n_part)
+{
+    const Stencil &S = H->st;
+    if (a.precision == CHEBFD_PREC_C128)
+        return launch_ti_lps<double, 1>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 1));
+    return launch_ti_lps<float, 2>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 2));
+}
+
+}  // namespace chebfd

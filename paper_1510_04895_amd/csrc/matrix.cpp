@@ -1,0 +1,340 @@
+// Sparse matrix handles: the topological-insulator Hamiltonian of Sec. 5.1
+// (Eq. (Ham)), CSR -> SELL-C-sigma conversion (Sec. 4.2), Gershgorin bounds
+// (Sec. 3.1 step 1) and upload to the device.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace chebfd {
+
+using cd = std::complex<double>;
+
+namespace {
+
+struct Entry {
+    int64_t c;
+    cd v;
+};
+
+// 4x4 blocks of Eq. (Ham) in the orbital basis o = 2 tau + s:
+// onsite G0 = diag(1, 1, -1, -1); hop[j][0] = -t/2 (G0 + i Gj) couples n to
+// n + e_j, hop[j][1] = -t/2 (G0 - i Gj) couples n to n - e_j.
+struct TiBlocks {
+    cd hop[3][2][4][4];
+    double g0[4];
+    TiBlocks(double t)
+    {
+        const cd I(0.0, 1.0);
+        const cd sig[3][2][2] = {{{0.0, 1.0}, {1.0, 0.0}},
+                                 {{0.0, -I}, {I, 0.0}},
+                                 {{1.0, 0.0}, {0.0, -1.0}}};
+        for (int o = 0; o < 4; ++o) g0[o] = (o < 2) ? 1.0 : -1.0;
+        for (int j = 0; j < 3; ++j)
+            for (int o = 0; o < 4; ++o)
+                for (int p = 0; p < 4; ++p) {
+                    const int to = o >> 1, so = o & 1, tp = p >> 1, sp = p & 1;
+                    const cd gj = (to != tp) ? sig[j][so][sp] : cd(0.0);
+                    const cd G0 = (o == p) ? cd(g0[o]) : cd(0.0);
+                    hop[j][0][o][p] = -0.5 * t * (G0 + I * gj);
+                    hop[j][1][o][p] = -0.5 * t * (G0 - I * gj);
+                }
+    }
+};
+
+// Merged, column-sorted entries of row (site, o) of the TI Hamiltonian.
+void ti_row(const TiBlocks &B, const int L[3], int pbc, double m, double vn, int64_t site,
+            int o, std::vector<Entry> &out)
+{
+    out.clear();
+    const int64_t lxy = (int64_t)L[0] * L[1];
+    const int r[3] = {(int)(site % L[0]), (int)((site / L[0]) % L[1]), (int)(site / lxy)};
+    out.push_back({4 * site + o, cd(m * B.g0[o] + vn)});
+    const int64_t stride[3] = {1, L[0], lxy};
+    for (int j = 0; j < 3; ++j)
+        for (int s = 0; s < 2; ++s) {
+            const int d = s == 0 ? 1 : -1;
+            int q = r[j] + d;
+            if (q < 0 || q >= L[j]) {
+                if (!((pbc >> j) & 1)) continue;
+                q = (q + L[j]) % L[j];
+            }
+            const int64_t nb = site + (int64_t)(q - r[j]) * stride[j];
+            for (int p = 0; p < 4; ++p) {
+                const cd v = B.hop[j][s][o][p];
+                if (v != cd(0.0)) out.push_back({4 * nb + p, v});
+            }
+        }
+    std::sort(out.begin(), out.end(), [](const Entry &a, const Entry &b) { return a.c < b.c; });
+    size_t w = 0;
+    for (size_t i = 0; i < out.size(); ++i) {
+        if (w > 0 && out[w - 1].c == out[i].c) out[w - 1].v += out[i].v;
+        else out[w++] = out[i];
+    }
+    out.resize(w);
+    out.erase(std::remove_if(out.begin(), out.end(), [](const Entry &e) { return e.v == cd(0.0); }),
+              out.end());
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return CHEBFD_OK;
+    CHEBFD_HIP(hipMalloc((void **)dst, src.size() * sizeof(T)));
+    CHEBFD_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CHEBFD_OK;
+}
+
+void free_matrix(chebfd_matrix *H)
+{
+    Sell &S = H->sell;
+    for (void *p : {(void *)S.chunk_ptr, (void *)S.chunk_len, (void *)S.perm, (void *)S.col,
+                    (void *)S.val64, (void *)S.val32, (void *)H->st.pot64, (void *)H->st.pot32})
+        if (p) (void)hipFree(p);
+}
+
+// Builds SELL-C-sigma from a row generator.  rowfn(i, entries) fills row i.
+template <typename RowFn>
+int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn)
+{
+    Sell &S = H->sell;
+    S.n = n;
+    S.C = C;
+    S.sigma = sigma;
+    S.nchunks = (n + C - 1) / C;
+    const int64_t nslots = S.nchunks * C;
+    // row lengths and the Gershgorin interval
+    std::vector<int32_t> len(n);
+    std::vector<Entry> row;
+    double lo = INFINITY, hi = -INFINITY;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rowfn(i, row);
+        len[i] = (int32_t)row.size();
+        nnz += (int64_t)row.size();
+        double d = 0.0, rad = 0.0;
+        for (const Entry &e : row) {
+            if (e.c == i) d += e.v.real();
+            else rad += std::abs(e.v);
+        }
+        lo = std::min(lo, d - rad);
+        hi = std::max(hi, d + rad);
+    }
+    H->g_lo = lo;
+    H->g_hi = hi;
+    S.nnz = nnz;
+    // sort rows by descending length inside each sigma window (stable)
+    std::vector<int32_t> perm(nslots, -1);
+    for (int64_t w0 = 0; w0 < n; w0 += sigma) {
+        const int64_t w1 = std::min(n, w0 + sigma);
+        std::vector<int32_t> ids(w1 - w0);
+        std::iota(ids.begin(), ids.end(), (int32_t)w0);
+        std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+        std::copy(ids.begin(), ids.end(), perm.begin() + w0);
+    }
+    std::vector<int64_t> cptr(S.nchunks + 1, 0);
+    std::vector<int32_t> clen(S.nchunks, 0);
+    int max_len = 0;
+    for (int64_t c = 0; c < S.nchunks; ++c) {
+        int w = 0;
+        for (int r = 0; r < C; ++r) {
+            const int32_t i = perm[c * C + r];
+            if (i >= 0) w = std::max(w, len[i]);
+        }
+        clen[c] = w;
+        max_len = std::max(max_len, w);
+        cptr[c + 1] = cptr[c] + (int64_t)w * C;
+    }
+    S.max_len = max_len;
+    S.stored = cptr[S.nchunks];
+    std::vector<int32_t> col(S.stored);
+    std::vector<double> v64(2 * S.stored, 0.0);
+    std::vector<float> v32(2 * S.stored, 0.0f);
+    for (int64_t c = 0; c < S.nchunks; ++c)
+        for (int r = 0; r < C; ++r) {
+            const int32_t i = perm[c * C + r];
+            // padding entries point at the row itself (an access the row
+            // makes anyway) with value zero; empty slots point at row 0
+            const int32_t self = i >= 0 ? i : 0;
+            if (i >= 0) rowfn(i, row);
+            else row.clear();
+            for (int j = 0; j < clen[c]; ++j) {
+                const int64_t e = cptr[c] + (int64_t)j * C + r;
+                if (j < (int)row.size()) {
+                    col[e] = (int32_t)row[j].c;
+                    v64[2 * e] = row[j].v.real();
+                    v64[2 * e + 1] = row[j].v.imag();
+                    v32[2 * e] = (float)row[j].v.real();
+                    v32[2 * e + 1] = (float)row[j].v.imag();
+                } else {
+                    col[e] = self;
+                }
+            }
+        }
+    int rc;
+    if ((rc = upload(&S.chunk_ptr, cptr)) || (rc = upload(&S.chunk_len, clen)) ||
+        (rc = upload(&S.perm, perm)) || (rc = upload(&S.col, col)) ||
+        (rc = upload(&S.val64, v64)) || (rc = upload(&S.val32, v32)))
+        return rc;
+    return CHEBFD_OK;
+}
+
+}  // namespace
+
+}  // namespace chebfd
+
+using namespace chebfd;
+
+extern "C" int chebfd_matrix_from_csr(chebfd_ctx *ctx, int64_t n, const int64_t *rowptr,
+                                      const int32_t *col, const double *val, int sell_C,
+                                      int sell_sigma, chebfd_matrix **out)
+{
+    if (!ctx || !out || !rowptr || (!col && n > 0) || (!val && n > 0))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_from_csr: NULL argument");
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t)INT32_MAX)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_from_csr: need 1 <= n < 2^31");
+    if (sell_C < 1 || sell_C > 64 || (sell_C & (sell_C - 1)) || sell_sigma < 1 ||
+        sell_sigma % sell_C)
+        return fail(CHEBFD_ERR_INVALID_ARG,
+                    "chebfd_matrix_from_csr: sell_C must be a power of two <= 64 and sell_sigma a multiple of it");
+    if (rowptr[0] != 0)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_from_csr: rowptr[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_from_csr: decreasing rowptr");
+    for (int64_t p = 0; p < rowptr[n]; ++p)
+        if (col[p] < 0 || col[p] >= n)
+            return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_from_csr: column index out of range");
+    CHEBFD_HIP(hipSetDevice(ctx->device));
+    auto *H = new chebfd_matrix();
+    H->storage = CHEBFD_STORAGE_SELL;
+    H->n = n;
+    H->device = ctx->device;
+    auto rowfn = [&](int64_t i, std::vector<Entry> &r) {
+        r.clear();
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            r.push_back({(int64_t)col[p], cd(val[2 * p], val[2 * p + 1])});
+    };
+    int rc = build_sell(H, n, sell_C, sell_sigma, rowfn);
+    if (rc) {
+        free_matrix(H);
+        delete H;
+        return rc;
+    }
+    *out = H;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc_mask, double t,
+                                double m, double V, uint64_t seed, int storage, int sell_C,
+                                int sell_sigma, chebfd_matrix **out)
+{
+    if (!ctx || !out) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_ti: NULL argument");
+    *out = nullptr;
+    if (Lx < 1 || Ly < 1 || Lz < 1)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_ti: lattice extents must be >= 1");
+    const int64_t nsites = (int64_t)Lx * Ly * Lz, n = 4 * nsites;
+    if (n >= (int64_t)INT32_MAX)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_ti: N must be < 2^31");
+    if (storage != CHEBFD_STORAGE_SELL && storage != CHEBFD_STORAGE_STENCIL)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_ti: unknown storage");
+    if (storage == CHEBFD_STORAGE_SELL &&
+        (sell_C < 1 || sell_C > 64 || (sell_C & (sell_C - 1)) || sell_sigma < 1 ||
+         sell_sigma % sell_C))
+        return fail(CHEBFD_ERR_INVALID_ARG,
+                    "chebfd_matrix_ti: sell_C must be a power of two <= 64 and sell_sigma a multiple of it");
+    CHEBFD_HIP(hipSetDevice(ctx->device));
+    const TiBlocks B(t);
+    const int L[3] = {Lx, Ly, Lz};
+    std::vector<double> pot(nsites);
+    for (int64_t s = 0; s < nsites; ++s) pot[s] = V * (u01(seed, 0, (uint64_t)s) - 0.5);
+    auto *H = new chebfd_matrix();
+    H->storage = storage;
+    H->n = n;
+    H->device = ctx->device;
+    auto rowfn = [&](int64_t i, std::vector<Entry> &r) {
+        ti_row(B, L, pbc_mask, m, pot[i / 4], i / 4, (int)(i % 4), r);
+    };
+    int rc = CHEBFD_OK;
+    if (storage == CHEBFD_STORAGE_SELL) {
+        rc = build_sell(H, n, sell_C, sell_sigma, rowfn);
+    } else {
+        Stencil &S = H->st;
+        S.L[0] = Lx;
+        S.L[1] = Ly;
+        S.L[2] = Lz;
+        S.pbc = pbc_mask;
+        S.t = t;
+        S.m = m;
+        // Gershgorin interval from the merged rows
+        std::vector<Entry> row;
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t i = 0; i < n; ++i) {
+            rowfn(i, row);
+            double d = 0.0, rad = 0.0;
+            for (const Entry &e : row) {
+                if (e.c == i) d += e.v.real();
+                else rad += std::abs(e.v);
+            }
+            lo = std::min(lo, d - rad);
+            hi = std::max(hi, d + rad);
+        }
+        H->g_lo = lo;
+        H->g_hi = hi;
+        std::vector<float> pot32(nsites);
+        for (int64_t s = 0; s < nsites; ++s) pot32[s] = (float)pot[s];
+        if (!(rc = upload(&S.pot64, pot))) rc = upload(&S.pot32, pot32);
+    }
+    if (rc) {
+        free_matrix(H);
+        delete H;
+        return rc;
+    }
+    *out = H;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_matrix_info(const chebfd_matrix *H, int64_t *n, int64_t *nnz,
+                                  int64_t *padded, double *g_lo, double *g_hi,
+                                  int64_t *matrix_bytes_c128, int64_t *matrix_bytes_c64)
+{
+    if (!H) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_matrix_info: NULL matrix");
+    const bool sell = H->storage == CHEBFD_STORAGE_SELL;
+    int64_t nz = sell ? H->sell.nnz : 0;
+    if (!sell) {
+        // 13 entries per row minus the missing neighbours of open boundaries
+        const int *L = H->st.L;
+        int64_t per = 0;
+        const int64_t ns = (int64_t)L[0] * L[1] * L[2];
+        for (int j = 0; j < 3; ++j) {
+            const int64_t links = ((H->st.pbc >> j) & 1) ? (int64_t)L[j] : (int64_t)L[j] - 1;
+            per += 2 * links * (ns / L[j]);   // directed links along j
+        }
+        nz = 4 * ns + 8 * per;   // on-site + 2 entries per orbital row per directed link
+    }
+    if (n) *n = H->n;
+    if (nnz) *nnz = nz;
+    if (padded) *padded = sell ? H->sell.stored : 0;
+    if (g_lo) *g_lo = H->g_lo;
+    if (g_hi) *g_hi = H->g_hi;
+    // one step reads every stored entry once: value + column index, plus the
+    // chunk pointers/lengths and the slot permutation
+    if (matrix_bytes_c128)
+        *matrix_bytes_c128 = sell ? H->sell.stored * (16 + 4) : (H->n / 4) * 8;
+    if (matrix_bytes_c64) *matrix_bytes_c64 = sell ? H->sell.stored * (8 + 4) : (H->n / 4) * 4;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_matrix_destroy(chebfd_matrix *H)
+{
+    if (!H) return CHEBFD_OK;
+    (void)hipSetDevice(H->device);
+    free_matrix(H);
+    delete H;
+    return CHEBFD_OK;
+}

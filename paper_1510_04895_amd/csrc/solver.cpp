@@ -1,0 +1,588 @@
+// The ChebFD scheme (Sec. 3.1, steps 1-8) on one GPU.
+//
+// Per outer iteration: the polynomial filter on the active block (N_p fused
+// launches, no host synchronisation), projection of the locked vectors out
+// of the block, SVQB orthonormalisation with refill (step 6), Rayleigh-Ritz
+// with Ritz vectors, H times Ritz vectors and FP64 residual norms (step 7),
+// ghost/convergence classification and locking (step 8).  The dense
+// contractions run on the FP64 matrix cores; the N_S x N_S eigenproblems on
+// the host.
+//
+// Readings where the paper leaves a choice (shared with the CPU reference):
+//  - an in-window Ritz pair is converged if r <= eps, converging if
+//    eps < r <= sqrt(eps), a ghost candidate otherwise;
+//  - exit after >= 2 iterations once no in-window pair is converging, the
+//    converged count has not changed, and the smallest remaining in-window
+//    residual has not fallen below half its previous value (ghosts: large
+//    residual that does not decrease);
+//  - the restart block is the set of Ritz vectors.
+// Locking (a refinement the paper lists in Sec. 6): converged in-window
+// pairs move to a locked set Q, later blocks are kept orthogonal to Q and
+// only the remaining columns are filtered.
+// Precision form (C64): the filter runs on complex64 blocks in FP32; Gram,
+// Rayleigh-Ritz and residuals are FP64 on the FP64-converted block.  When the
+// in-window residuals reach `polish_switch` or stop improving, the block is
+// promoted to complex128 and the FP64 iteration continues to eps.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+struct chebfd_result {
+    std::vector<double> evals, res, evecs;
+    chebfd_stats stats{};
+};
+
+namespace chebfd {
+namespace {
+
+using clk = std::chrono::steady_clock;
+static double secs(clk::time_point a, clk::time_point b)
+{
+    return std::chrono::duration<double>(b - a).count();
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t blk64 = 0, blk32 = 0;   // bytes of one c128 / c64 block
+    size_t off_b[4] = {0, 0, 0, 0};
+    size_t off_x32 = 0, off_q = 0, off_small = 0, total = 0;
+    size_t small = 0;
+};
+
+Layout layout(int64_t n, const chebfd_params &p)
+{
+    Layout L;
+    L.blk64 = align256((size_t)n * p.n_s * 16);
+    L.blk32 = align256((size_t)n * p.n_s * 8);
+    size_t off = 0;
+    // three c128 blocks (in the C64 form the first one also hosts the two
+    // c64 filter scratch blocks U32, W32)
+    for (int i = 0; i < 3; ++i) {
+        L.off_b[i] = off;
+        off += L.blk64;
+    }
+    if (p.precision == CHEBFD_PREC_C64) {
+        L.off_x32 = off;
+        off += L.blk32;
+    }
+    if (p.lock) {
+        L.off_q = off;
+        off += L.blk64;
+    }
+    // small device matrices: S (n_s^2 c128), Tr (4 n_s^2 doubles), theta,
+    // residuals (n_s each), column index list (n_s int32)
+    const size_t ns = (size_t)p.n_s;
+    L.small = align256(ns * ns * 16) + align256(4 * ns * ns * 8) + 2 * align256(ns * 8) +
+              align256(ns * 4) + align256(ns * ns * 16);
+    L.off_small = off;
+    off += L.small;
+    L.total = off;
+    return L;
+}
+
+struct Solver {
+    chebfd_ctx *ctx;
+    const chebfd_matrix *H;
+    chebfd_params p;
+    int64_t n;
+    int ns;
+    char *ws;
+    Layout L;
+    // device small buffers
+    double *dS = nullptr, *dTr = nullptr, *dTheta = nullptr, *dRes = nullptr, *dS2 = nullptr;
+    int32_t *dIdx = nullptr;
+    std::vector<double> gamma;
+    double a = 0, b = 0;
+    chebfd_stats st{};
+    uint64_t refill_ctr = 0;
+
+    int sync() { CHEBFD_HIP(hipStreamSynchronize(ctx->stream)); return CHEBFD_OK; }
+
+    int down(void *dst, const void *src, size_t bytes)
+    {
+        CHEBFD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+        return sync();
+    }
+    int up(void *dst, const void *src, size_t bytes)
+    {
+        CHEBFD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+        return CHEBFD_OK;
+    }
+
+    // Uploads the real (2k x 2m) expansion of a complex k x m host matrix.
+    int upload_T(const std::vector<double> &T, int k, int m)
+    {
+        std::vector<double> Tr((size_t)4 * k * m);
+        const size_t mc = 2 * (size_t)m;
+        for (int r = 0; r < k; ++r)
+            for (int c = 0; c < m; ++c) {
+                const double re = T[2 * ((size_t)r * m + c)], im = T[2 * ((size_t)r * m + c) + 1];
+                Tr[(2 * r) * mc + 2 * c] = re;
+                Tr[(2 * r) * mc + 2 * c + 1] = im;
+                Tr[(2 * r + 1) * mc + 2 * c] = -im;
+                Tr[(2 * r + 1) * mc + 2 * c + 1] = re;
+            }
+        int rc = up(dTr, Tr.data(), Tr.size() * 8);
+        if (rc) return rc;
+        return sync();   // the host vector goes out of scope
+    }
+
+    // S = A^H B on the device, copied to the host (k x m complex).
+    int gram_host(int prec_a, const void *A, int k, int prec_b, const void *B, int m,
+                  std::vector<double> &S)
+    {
+        int rc;
+        if (prec_a != prec_b) return fail(CHEBFD_ERR_UNSUPPORTED, "mixed-precision Gram");
+        if ((rc = launch_gram(ctx, prec_a, A, ns, k, B, ns, m, n, dS))) return rc;
+        S.resize((size_t)2 * k * m);
+        return down(S.data(), dS, S.size() * 8);
+    }
+
+    // X <- X - Q (Q^H X) for the nl locked columns (c128 Q).
+    int project_locked(int prec, void *X, int k, int nl, void *Q)
+    {
+        if (nl == 0 || k == 0) return CHEBFD_OK;
+        int rc;
+        void *src = X;
+        std::vector<double> S;
+        if (prec == CHEBFD_PREC_C64) return fail(CHEBFD_ERR_UNSUPPORTED, "locking in c64 phase");
+        if ((rc = gram_host(CHEBFD_PREC_C128, Q, nl, CHEBFD_PREC_C128, src, k, S))) return rc;
+        if ((rc = upload_T(S, nl, k))) return rc;
+        return launch_block_times(ctx, CHEBFD_PREC_C128, Q, ns, n, nl, dTr, k, prec, X, ns, 1);
+    }
+
+    // SVQB (Sec. 3.1 step 6): X (k columns) -> orthonormal, via scratch Y.
+    // On return *X_out points at the buffer holding the result.
+    int svqb(int prec, void **X, void **Y, int k, int nl, void *Q)
+    {
+        int clean = 0;
+        std::vector<double> S, w, T;
+        for (int pass = 0; pass < 8 && clean < 2; ++pass) {
+            int rc;
+            if ((rc = gram_host(prec, *X, k, prec, *X, k, S))) return rc;
+            std::vector<double> d(k);
+            for (int i = 0; i < k; ++i) {
+                const double s = S[2 * ((size_t)i * k + i)];
+                if (!std::isfinite(s)) return fail(CHEBFD_ERR_NONFINITE, "non-finite Gram diagonal");
+                d[i] = s > 0.0 ? 1.0 / std::sqrt(s) : 0.0;
+            }
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j) {
+                    S[2 * ((size_t)i * k + j)] *= d[i] * d[j];
+                    S[2 * ((size_t)i * k + j) + 1] *= d[i] * d[j];
+                }
+            if (herm_eig(k, S, w) != 0) return fail(CHEBFD_ERR_NONFINITE, "SVQB eigensolver failed");
+            const double tmax = w[k - 1];
+            // T = D U Theta^{-1/2}, kept directions, largest first
+            T.assign((size_t)2 * k * k, 0.0);
+            int keep = 0;
+            for (int j = k - 1; j >= 0; --j) {
+                if (!(w[j] > 1e-12 * tmax)) continue;
+                const double f = 1.0 / std::sqrt(w[j]);
+                for (int i = 0; i < k; ++i) {
+                    T[2 * ((size_t)i * k + keep)] = d[i] * S[2 * ((size_t)i * k + j)] * f;
+                    T[2 * ((size_t)i * k + keep) + 1] = d[i] * S[2 * ((size_t)i * k + j) + 1] * f;
+                }
+                ++keep;
+            }
+            if ((rc = upload_T(T, k, k))) return rc;
+            if ((rc = launch_block_times(ctx, prec, *X, ns, n, k, dTr, k, prec, *Y, ns, 0)))
+                return rc;
+            std::swap(*X, *Y);
+            if (keep < k) {
+                // refill the dropped directions with random vectors (stream 3)
+                const uint64_t off = (uint64_t)(++refill_ctr) * (uint64_t)n * (uint64_t)ns;
+                if ((rc = launch_random(ctx, prec, *X, n, ns, ns, keep, k - keep, p.seed, 3, off)))
+                    return rc;
+                st.refilled += k - keep;
+                if ((rc = project_locked(prec, *X, k, nl, Q))) return rc;
+                clean = 0;
+            } else {
+                ++clean;
+            }
+        }
+        return CHEBFD_OK;
+    }
+
+    int run(chebfd_result *out)
+    {
+        const auto t0 = clk::now();
+        char *base = ws;
+        const bool c64 = p.precision == CHEBFD_PREC_C64;
+        void *B[3] = {base + L.off_b[0], base + L.off_b[1], base + L.off_b[2]};
+        void *Q = p.lock ? (void *)(base + L.off_q) : nullptr;
+        char *sm = base + L.off_small;
+        const size_t nsz = (size_t)ns;
+        dS = (double *)sm;
+        sm += align256(nsz * nsz * 16);
+        dTr = (double *)sm;
+        sm += align256(4 * nsz * nsz * 8);
+        dTheta = (double *)sm;
+        sm += align256(nsz * 8);
+        dRes = (double *)sm;
+        sm += align256(nsz * 8);
+        dIdx = (int32_t *)sm;
+        sm += align256(nsz * 4);
+        dS2 = (double *)sm;
+
+        // filter buffers for each phase
+        void *X32 = c64 ? (void *)(base + L.off_x32) : nullptr;
+        void *U32 = B[0], *W32 = (char *)B[0] + L.blk32;
+        // c128 roles: X, U, W rotate among B[0..2]
+        void *X = B[1], *U = B[2], *W = B[0];
+        int prec = c64 ? CHEBFD_PREC_C64 : CHEBFD_PREC_C128;
+        int rc;
+        if (c64) rc = launch_random(ctx, CHEBFD_PREC_C64, X32, n, ns, ns, 0, ns, p.seed, 1, 0);
+        else rc = launch_random(ctx, CHEBFD_PREC_C128, X, n, ns, ns, 0, ns, p.seed, 1, 0);
+        if (rc) return rc;
+
+        int n_lock = 0, prev_conv = -1, status = CHEBFD_WARN_NOT_CONVERGED;
+        double prev_rmin = INFINITY, prev_worst = INFINITY;
+        std::vector<double> lock_vals, lock_res;
+        std::vector<double> theta, res, S, w;
+        int last_active = ns;
+        std::vector<int> keep_idx, conv_idx;
+        const double seps = std::sqrt(p.eps);
+        int it;
+        for (it = 1; it <= p.max_iter; ++it) {
+            const int k = ns - n_lock;   // active columns
+            last_active = k;
+            if (k <= 0) break;
+            // ---------------- step 5: filter
+            auto ta = clk::now();
+            if (prec == CHEBFD_PREC_C64) {
+                rc = filter_apply(ctx, H, CHEBFD_PREC_C64, gamma.data(), p.n_p, a, b, X32, U32,
+                                  W32, k & 1 ? k + 1 : k, ns, nullptr);
+                ++st.iterations_c64;
+            } else {
+                rc = filter_apply(ctx, H, CHEBFD_PREC_C128, gamma.data(), p.n_p, a, b, X, U, W, k,
+                                  ns, nullptr);
+            }
+            if (rc) return rc;
+            st.n_mvm += (int64_t)k * p.n_p;
+            if ((rc = sync())) return rc;
+            auto tb = clk::now();
+            st.t_filter += secs(ta, tb);
+            // ---------------- step 6: orthogonalise (FP64 on the converted block)
+            if (prec == CHEBFD_PREC_C64) {
+                // X <- fp64(X32); orthogonalise in c128
+                if ((rc = launch_convert(ctx, CHEBFD_PREC_C64, X32, CHEBFD_PREC_C128, X, n, k, ns, ns)))
+                    return rc;
+            }
+            if ((rc = project_locked(CHEBFD_PREC_C128, X, k, n_lock, Q))) return rc;
+            if ((rc = svqb(CHEBFD_PREC_C128, &X, &U, k, n_lock, Q))) return rc;
+            auto tc = clk::now();
+            st.t_ortho += secs(tb, tc);
+            // ---------------- step 7: Rayleigh-Ritz
+            StepArgs s{};
+            s.mode = MODE_APPLY;
+            s.precision = CHEBFD_PREC_C128;
+            s.u = X;
+            s.wout = U;
+            s.n = n;
+            s.n_s = k;
+            s.ld = ns;
+            s.s_h = 1.0;
+            s.s_u = 0.0;
+            if ((rc = launch_step(ctx, H, s, nullptr))) return rc;        // U = H X
+            if ((rc = gram_host(CHEBFD_PREC_C128, X, k, CHEBFD_PREC_C128, U, k, S))) return rc;
+            if (herm_eig(k, S, theta) != 0) return fail(CHEBFD_ERR_NONFINITE, "Rayleigh-Ritz eigensolver failed");
+            if ((rc = upload_T(S, k, k))) return rc;
+            // W = X Ug (Ritz vectors), X = U Ug (H times Ritz vectors)
+            if ((rc = launch_block_times(ctx, CHEBFD_PREC_C128, X, ns, n, k, dTr, k, CHEBFD_PREC_C128, W, ns, 0)))
+                return rc;
+            if ((rc = launch_block_times(ctx, CHEBFD_PREC_C128, U, ns, n, k, dTr, k, CHEBFD_PREC_C128, X, ns, 0)))
+                return rc;
+            if ((rc = up(dTheta, theta.data(), (size_t)k * 8))) return rc;
+            if ((rc = launch_residuals(ctx, CHEBFD_PREC_C128, W, X, n, k, ns, dTheta, dRes))) return rc;
+            res.resize(k);
+            if ((rc = down(res.data(), dRes, (size_t)k * 8))) return rc;
+            for (int j = 0; j < k; ++j)
+                if (!std::isfinite(theta[j]) || !std::isfinite(res[j]))
+                    return fail(CHEBFD_ERR_NONFINITE, "non-finite Ritz pair");
+            auto td = clk::now();
+            st.t_rr += secs(tc, td);
+            // V now in W; new block = V
+            std::swap(X, W);
+            // ---------------- step 8: classify
+            int nconv = 0, nconving = 0;
+            double rmin = INFINITY, worst = 0.0;
+            keep_idx.clear();
+            conv_idx.clear();
+            for (int j = 0; j < k; ++j) {
+                const bool in = theta[j] >= p.lam_lo && theta[j] <= p.lam_hi;
+                if (in && res[j] <= p.eps) {
+                    ++nconv;
+                    conv_idx.push_back(j);
+                    continue;
+                }
+                keep_idx.push_back(j);
+                if (!in) continue;
+                if (res[j] <= seps) ++nconving;
+                rmin = std::min(rmin, res[j]);
+                if (res[j] <= seps) worst = std::max(worst, res[j]);
+            }
+            if (prec == CHEBFD_PREC_C64) {
+                // FP32 phase: switch to FP64 once the in-window residuals sit
+                // below polish_switch or stop improving
+                double mx = 0.0;
+                for (int j = 0; j < k; ++j)
+                    if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= seps)
+                        mx = std::max(mx, res[j]);
+                const int ngood = nconv + nconving;
+                const bool below = ngood > 0 && mx <= p.polish_switch;
+                const bool stalled = it >= 2 && ngood > 0 && mx > 0.5 * prev_worst;
+                prev_worst = ngood > 0 ? mx : INFINITY;
+                if (below || stalled) {
+                    prec = CHEBFD_PREC_C128;   // X (c128 Ritz vectors) continues in FP64
+                    void *others[2];
+                    int q = 0;
+                    for (void *bb : {B[0], B[1], B[2]})
+                        if (bb != X && q < 2) others[q++] = bb;
+                    U = others[0];
+                    W = others[1];
+                    // the count to confirm is the number of in-window pairs
+                    // the FP32 sweep brought below sqrt(eps)
+                    prev_conv = ngood;
+                    prev_rmin = rmin;
+                } else {
+                    // X32 <- Ritz vectors
+                    if ((rc = launch_convert(ctx, CHEBFD_PREC_C128, X, CHEBFD_PREC_C64, X32, n, k, ns, ns)))
+                        return rc;
+                    if (k & 1) {
+                        // keep the padding column of an odd block defined
+                        if ((rc = launch_random(ctx, CHEBFD_PREC_C64, X32, n, ns, ns, k, 1, p.seed, 3, 0)))
+                            return rc;
+                    }
+                }
+                continue;
+            }
+            if (p.lock && !conv_idx.empty()) {
+                // Q[:, n_lock + j] = V[:, conv_j]; compact the rest into U
+                std::vector<int32_t> idx(conv_idx.begin(), conv_idx.end());
+                if ((rc = up(dIdx, idx.data(), idx.size() * 4))) return rc;
+                if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, X, ns, Q, ns, n_lock, dIdx, n,
+                                             (int64_t)idx.size())))
+                    return rc;
+                if ((rc = sync())) return rc;
+                for (int j : conv_idx) {
+                    lock_vals.push_back(theta[j]);
+                    lock_res.push_back(res[j]);
+                }
+                n_lock += (int)conv_idx.size();
+                if (!keep_idx.empty()) {
+                    std::vector<int32_t> kid(keep_idx.begin(), keep_idx.end());
+                    if ((rc = up(dIdx, kid.data(), kid.size() * 4))) return rc;
+                    if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, X, ns, U, ns, 0, dIdx, n,
+                                                 (int64_t)kid.size())))
+                        return rc;
+                    if ((rc = sync())) return rc;
+                    std::swap(X, U);
+                }
+            }
+            const int total_conv = p.lock ? n_lock : nconv;
+            const bool stagnant = (rmin == INFINITY) || (rmin >= 0.5 * prev_rmin);
+            if (it >= 2 && nconving == 0 && total_conv == prev_conv && stagnant) {
+                status = CHEBFD_OK;
+                break;
+            }
+            prev_conv = total_conv;
+            prev_rmin = rmin;
+            if (p.lock && n_lock >= ns) {
+                status = CHEBFD_WARN_SEARCH_SPACE_TOO_SMALL;
+                break;
+            }
+        }
+        st.iterations = std::min(it, p.max_iter);
+        // ---------------- collect converged in-window pairs
+        std::vector<std::pair<double, int>> order;   // (lambda, source)
+        std::vector<double> vals, rs;
+        std::vector<int> src_col;
+        std::vector<char> from_q;
+        if (p.lock) {
+            for (int j = 0; j < n_lock; ++j) {
+                vals.push_back(lock_vals[j]);
+                rs.push_back(lock_res[j]);
+                src_col.push_back(j);
+                from_q.push_back(1);
+            }
+        }
+        if (!p.lock || status != CHEBFD_OK) {
+            // unlocked converged pairs of the last Rayleigh-Ritz (block X)
+            for (size_t q = 0; q < (p.lock ? keep_idx.size() : (size_t)last_active); ++q) {
+                const int j = p.lock ? keep_idx[q] : (int)q;
+                if (j >= (int)theta.size()) break;
+                if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= p.eps &&
+                    prec == CHEBFD_PREC_C128) {
+                    vals.push_back(theta[j]);
+                    rs.push_back(res[j]);
+                    src_col.push_back(p.lock ? (int)q : j);
+                    from_q.push_back(0);
+                }
+            }
+        }
+        std::vector<int> ord(vals.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return vals[x] < vals[y]; });
+        const int nf = (int)ord.size();
+        out->evals.resize(nf);
+        out->res.resize(nf);
+        double maxr = 0.0;
+        for (int i = 0; i < nf; ++i) {
+            out->evals[i] = vals[ord[i]];
+            out->res[i] = rs[ord[i]];
+            maxr = std::max(maxr, out->res[i]);
+        }
+        if (p.vectors && nf > 0) {
+            // gather the selected columns, in ascending order, into a
+            // contiguous n x nf block in a free buffer and download it
+            void *dst = nullptr;
+            for (void *bb : {B[0], B[1], B[2]})
+                if (bb != X) {
+                    dst = bb;
+                    break;
+                }
+            for (int i = 0; i < nf; ++i) {
+                const int o = ord[i];
+                int32_t one = src_col[o];
+                if ((rc = up(dIdx, &one, 4))) return rc;
+                if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, from_q[o] ? Q : X, ns, dst, nf,
+                                             i, dIdx, n, 1)))
+                    return rc;
+                if ((rc = sync())) return rc;
+            }
+            out->evecs.resize((size_t)n * nf * 2);
+            if ((rc = down(out->evecs.data(), dst, out->evecs.size() * 8))) return rc;
+        }
+        st.n_found = nf;
+        st.n_locked = n_lock;
+        st.a = a;
+        st.b = b;
+        st.max_residual = maxr;
+        st.t_total = secs(t0, clk::now());
+        out->stats = st;
+        return status;
+    }
+};
+
+}  // namespace
+}  // namespace chebfd
+
+using namespace chebfd;
+
+extern "C" int chebfd_params_default(chebfd_params *p)
+{
+    if (!p) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_params_default: NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->n_s = 32;
+    p->n_p = 200;
+    p->kernel = CHEBFD_KERNEL_LANCZOS;
+    p->mu = 2.0;
+    p->eps = 1e-9;
+    p->max_iter = 50;
+    p->precision = CHEBFD_PREC_C128;
+    p->lock = 1;
+    p->a = NAN;
+    p->b = NAN;
+    p->seed = 1;
+    p->gamma_corr = nullptr;
+    p->polish_switch = 1e-6;
+    p->vectors = 1;
+    return CHEBFD_OK;
+}
+
+static int check_params(const chebfd_matrix *H, const chebfd_params *p)
+{
+    if (!H || !p) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: NULL argument");
+    if (!(p->lam_lo < p->lam_hi) || !std::isfinite(p->lam_lo) || !std::isfinite(p->lam_hi))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: need finite lam_lo < lam_hi");
+    if (p->n_s < 1 || p->n_s > 1024 || p->n_s > H->n)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: need 1 <= n_s <= min(1024, N)");
+    if (p->n_p < 2) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: n_p must be >= 2");
+    if (p->kernel < 0 || p->kernel > 3) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: unknown kernel");
+    if (!(p->eps > 0.0)) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: eps must be > 0");
+    if (p->max_iter < 1) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: max_iter must be >= 1");
+    if (p->precision != CHEBFD_PREC_C128 && p->precision != CHEBFD_PREC_C64)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: unknown precision");
+    if (p->precision == CHEBFD_PREC_C64 && (p->n_s & 1))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: the c64 form needs an even n_s");
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_solve_workspace_size(const chebfd_matrix *H, const chebfd_params *p,
+                                           int64_t *bytes)
+{
+    int rc = check_params(H, p);
+    if (rc) return rc;
+    if (!bytes) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve_workspace_size: NULL bytes");
+    *bytes = (int64_t)layout(H->n, *p).total;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_solve(chebfd_ctx *ctx, const chebfd_matrix *H, const chebfd_params *p,
+                            void *workspace, int64_t workspace_bytes, chebfd_result **out)
+{
+    if (!ctx || !out) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: NULL argument");
+    *out = nullptr;
+    int rc = check_params(H, p);
+    if (rc) return rc;
+    Solver S;
+    S.ctx = ctx;
+    S.H = H;
+    S.p = *p;
+    S.n = H->n;
+    S.ns = p->n_s;
+    S.L = layout(H->n, *p);
+    if (!workspace || workspace_bytes < (int64_t)S.L.total || ((uintptr_t)workspace & 255))
+        return fail(CHEBFD_ERR_WORKSPACE, "chebfd_solve: workspace missing, too small or not 256-byte aligned");
+    S.ws = (char *)workspace;
+    S.a = std::isnan(p->a) ? H->g_lo : p->a;
+    S.b = std::isnan(p->b) ? H->g_hi : p->b;
+    if (!(S.a < S.b)) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: empty spectral interval");
+    if (p->lam_hi <= S.a || p->lam_lo >= S.b)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: window outside the spectral interval");
+    S.gamma.resize(p->n_p + 1);
+    if ((rc = chebfd_coeffs(p->lam_lo, p->lam_hi, S.a, S.b, p->n_p, p->kernel, p->mu, S.gamma.data())))
+        return rc;
+    if (p->gamma_corr)
+        for (int k = 0; k <= p->n_p; ++k) {
+            if (!std::isfinite(p->gamma_corr[k]))
+                return fail(CHEBFD_ERR_NONFINITE, "chebfd_solve: non-finite coefficient correction");
+            S.gamma[k] *= 1.0 + p->gamma_corr[k];
+        }
+    CHEBFD_HIP(hipSetDevice(ctx->device));
+    auto *res = new chebfd_result();
+    rc = S.run(res);
+    if (rc < 0) {
+        delete res;
+        return rc;
+    }
+    *out = res;
+    return rc;
+}
+
+extern "C" int chebfd_result_get(const chebfd_result *r, int64_t *n_found, const double **evals,
+                                 const double **residuals, const double **evecs,
+                                 chebfd_stats *stats)
+{
+    if (!r) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_result_get: NULL result");
+    if (n_found) *n_found = (int64_t)r->evals.size();
+    if (evals) *evals = r->evals.data();
+    if (residuals) *residuals = r->res.data();
+    if (evecs) *evecs = r->evecs.empty() ? nullptr : r->evecs.data();
+    if (stats) *stats = r->stats;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_result_destroy(chebfd_result *r)
+{
+    delete r;
+    return CHEBFD_OK;
+}

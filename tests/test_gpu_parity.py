@@ -1,0 +1,259 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU reference,
+element by element on the same seeded inputs.
+
+Tolerances: FP64 paths 1e-12 relative (Frobenius) -- the filter is a
+polynomial of degree n_p in a matrix of norm <= 1 after scaling, so rounding
+grows at most linearly in n_p; FP32 paths sqrt(n_p) * 2^-24 * 30 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import chebfd_inputs as inp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1510_04895_amd import binding as B
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    return torch, B, ctx
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(torch, X, dtype=None, ld=None):
+    n, k = X.shape
+    ld = ld or k
+    dt = dtype or torch.complex128
+    buf = torch.zeros((n, ld), dtype=dt, device="cuda")
+    buf[:, :k] = torch.from_numpy(np.ascontiguousarray(X)).to(dt)
+    return buf
+
+
+def csr_of(orc_H):
+    return orc_H.rowptr, orc_H.col, orc_H.val
+
+
+# ----------------------------------------------------------------- matrices
+@pytest.mark.parametrize("L,pbc", [((4, 4, 4), 3), ((3, 5, 2), 7), ((2, 2, 3), 3), ((8, 8, 8), 3)])
+def test_ti_matrix_spmm_vs_reference(env, orc, L, pbc):
+    """The library's own TI generator (SELL and stencil) applied to a block
+    equals the reference CSR times the block."""
+    torch, B, ctx = env
+    Hr = orc.ti_hamiltonian(*L, pbc=pbc, V=1.0, seed=5)
+    X = inp.random_block(Hr.n, 19, seed=1)
+    ref = orc.spmm(Hr, X)
+    for storage in (B.STORAGE_SELL, B.STORAGE_STENCIL):
+        H = B.Matrix.ti(ctx, L, pbc=pbc, V=1.0, seed=5, storage=storage)
+        info = H.info()
+        ga, gb = orc.gershgorin(Hr)
+        assert info["g_lo"] == pytest.approx(ga, abs=1e-13)
+        assert info["g_hi"] == pytest.approx(gb, abs=1e-13)
+        Xd = to_dev(torch, X, ld=21)
+        Yd = torch.zeros_like(Xd)
+        B.chebfd_spmm(ctx, H, Xd[:, :19], Yd[:, :19])
+        torch.cuda.synchronize()
+        assert relerr(Yd[:, :19].cpu().numpy(), ref) < 1e-14
+        if storage == B.STORAGE_SELL:
+            assert info["nnz"] == Hr.nnz
+
+
+def test_from_csr_ragged_rows(env, orc):
+    """SELL-C-sigma from a random Hermitian CSR with ragged rows (sigma
+    sorting and padding exercised) against the reference spmm."""
+    torch, B, ctx = env
+    rp, col, val = inp.random_hermitian_csr(997, seed=3, min_row=1, max_row=40)
+    Hr = orc.CSR(997, rp, col, val)
+    X = inp.random_block(997, 33, seed=2)
+    ref = orc.spmm(Hr, X)
+    for C, sig in [(32, 256), (8, 8), (1, 1), (64, 128)]:
+        H = B.Matrix.from_csr(ctx, rp, col, val, sell_C=C, sell_sigma=sig)
+        Xd = to_dev(torch, X)
+        Yd = torch.zeros_like(Xd)
+        B.chebfd_spmm(ctx, H, Xd, Yd, s_h=0.5, s_u=-0.25)
+        torch.cuda.synchronize()
+        assert relerr(Yd.cpu().numpy(), 0.5 * ref - 0.25 * X) < 1e-14
+
+
+# ------------------------------------------------------------------- filter
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+@pytest.mark.parametrize("n_s,ld,n_p", [(37, 40, 23), (1, 1, 2), (256, 256, 6), (16, 16, 3)])
+def test_filter_c128_vs_reference(env, orc, storage, n_s, ld, n_p):
+    torch, B, ctx = env
+    L = (6, 5, 4)
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=2)
+    a, b = orc.gershgorin(Hr)
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=2, storage=st)
+    X = inp.random_block(Hr.n, n_s, seed=7)
+    gam = inp.random_gamma(n_p, seed=3)
+    ref, mref = orc.filter_block(Hr, a, b, gam, X, moments=True)
+    Xd = to_dev(torch, X, ld=ld)
+    Ud = torch.zeros_like(Xd)
+    Wd = torch.zeros_like(Xd)
+    mom = torch.zeros((2 * n_p + 1, n_s), dtype=torch.float64, device="cuda")
+    B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom, n_s=n_s)
+    torch.cuda.synchronize()
+    got = Xd[:, :n_s].cpu().numpy()
+    assert relerr(got, ref) < 1e-12 * max(1, n_p)
+    # columns beyond n_s untouched
+    assert torch.count_nonzero(Xd[:, n_s:]).item() == 0
+    m = mom.cpu().numpy()
+    assert np.abs(m - mref).max() < 1e-11 * np.abs(mref[0]).max() * max(1, n_p)
+
+
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+def test_filter_c64_vs_reference(env, orc, storage):
+    torch, B, ctx = env
+    L = (6, 6, 4)
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=4)
+    a, b = orc.gershgorin(Hr)
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=4, storage=st)
+    n_s, n_p = 34, 60
+    X = inp.random_block(Hr.n, n_s, seed=8).astype(np.complex64).astype(np.complex128)
+    gam = orc.gamma(-0.5, 0.5, a, b, n_p)
+    ref = orc.filter_block(Hr, a, b, gam, X)
+    Xd = to_dev(torch, X, dtype=torch.complex64)
+    Ud = torch.zeros_like(Xd)
+    Wd = torch.zeros_like(Xd)
+    B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
+    torch.cuda.synchronize()
+    got = Xd.cpu().numpy().astype(np.complex128)
+    tol = 30 * math.sqrt(n_p) * 2.0 ** -24
+    assert relerr(got, ref) < tol
+
+
+def test_filter_full_block_equals_column_subset(env, orc):
+    """Columns are independent: the 256-column launch (the throughput
+    configuration's shape) gives bitwise the same columns as narrower
+    launches, which are checked against the reference above."""
+    torch, B, ctx = env
+    L = (8, 8, 6)
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1)
+    info = H.info()
+    a, b = info["g_lo"], info["g_hi"]
+    n = info["n"]
+    X = inp.random_block(n, 256, seed=5)
+    gam = inp.random_gamma(9, seed=2)
+    outs = []
+    for cols in (256, 40, 8):
+        Xd = to_dev(torch, X[:, :cols])
+        Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
+        B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
+        outs.append(Xd.cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[0][:, :40], outs[1])
+    assert np.array_equal(outs[0][:, :8], outs[2])
+
+
+def test_filter_invalid_arguments(env):
+    torch, B, ctx = env
+    H = B.Matrix.ti(ctx, (2, 2, 2), V=1.0)
+    X = torch.zeros((32, 4), dtype=torch.complex128, device="cuda")
+    U, W = torch.zeros_like(X), torch.zeros_like(X)
+    with pytest.raises(B.ChebFDError):
+        B.chebfd_filter_apply(ctx, H, np.ones(2), -1, 1, X, U, W)       # n_p = 1
+    with pytest.raises(B.ChebFDError):
+        B.chebfd_filter_apply(ctx, H, np.ones(5), 1, -1, X, U, W)       # a > b
+    with pytest.raises(B.ChebFDError):
+        B.chebfd_filter_apply(ctx, H, np.ones(5), -1, 1, X, X, W)       # aliasing
+    X32 = torch.zeros((32, 3), dtype=torch.complex64, device="cuda")
+    with pytest.raises(B.ChebFDError):
+        B.chebfd_filter_apply(ctx, H, np.ones(5), -1, 1, X32, X32.clone(), X32.clone())  # odd c64
+
+
+# -------------------------------------------------------------------- dense
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,ka,kb", [(3001, 37, 37), (64, 5, 9), (20000, 128, 128)])
+def test_gram_vs_lapack(env, dt, n, ka, kb):
+    torch, B, ctx = env
+    A = inp.random_block(n, ka, seed=1)
+    Bm = inp.random_block(n, kb, seed=2)
+    tdt = torch.complex128 if dt == "c128" else torch.complex64
+    if dt == "c64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        Bm = Bm.astype(np.complex64).astype(np.complex128)
+    Ad, Bd = to_dev(torch, A, tdt), to_dev(torch, Bm, tdt)
+    S = torch.zeros((ka, kb), dtype=torch.complex128, device="cuda")
+    B.chebfd_gram(ctx, Ad, Bd, S)
+    torch.cuda.synchronize()
+    ref = A.conj().T @ Bm
+    assert relerr(S.cpu().numpy(), ref) < 1e-14
+
+
+@pytest.mark.parametrize("n,k,m,sub", [(5000, 37, 21, False), (130, 64, 64, True),
+                                       (20000, 256, 256, False)])
+def test_block_times_vs_lapack(env, n, k, m, sub):
+    torch, B, ctx = env
+    A = inp.random_block(n, k, seed=3)
+    T = inp.random_block(k, m, seed=4)
+    C0 = inp.random_block(n, m, seed=5)
+    Ad = to_dev(torch, A)
+    Td = torch.from_numpy(T).cuda()
+    Cd = to_dev(torch, C0)
+    B.chebfd_block_times(ctx, Ad, Td, Cd, subtract=sub)
+    torch.cuda.synchronize()
+    ref = (C0 - A @ T) if sub else A @ T
+    assert relerr(Cd.cpu().numpy(), ref) < 1e-14
+
+
+def test_residual_norms(env):
+    torch, B, ctx = env
+    V = inp.random_block(4000, 20, seed=1)
+    HV = inp.random_block(4000, 20, seed=2)
+    th = np.linspace(-1, 1, 20)
+    r = B.chebfd_residual_norms(ctx, to_dev(torch, V), to_dev(torch, HV), th)
+    ref = np.linalg.norm(HV - V * th, axis=0)
+    assert np.abs(r - ref).max() < 1e-12 * ref.max()
+
+
+def test_random_block_bitwise(env, orc):
+    """Counter-based random block: identical bits to the reference generator."""
+    torch, B, ctx = env
+    X = torch.zeros((300, 7), dtype=torch.complex128, device="cuda")
+    B.chebfd_random_block(ctx, X, seed=11, stream=1, offset=5)
+    torch.cuda.synchronize()
+    ref = orc.random_block(300, 7, seed=11, stream=1, offset=5)
+    assert np.array_equal(X.cpu().numpy(), ref)
+
+
+# -------------------------------------------------------------------- solve
+def _dense_window(orc, Hr, n_in):
+    """Window [-d, d] holding the n_in eigenvalues of smallest modulus, with
+    d halfway to the next one (the oracle's own dense diagonalisation)."""
+    w, _ = orc.jacobi_herm(Hr.dense())
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[n_in - 1] + aw[n_in])
+    return w, d
+
+
+@pytest.mark.parametrize("storage,prec,lock", [("sell", "c128", 1), ("stencil", "c128", 0),
+                                               ("sell", "c64", 1), ("stencil", "c64", 1)])
+def test_solve_small_lattice_vs_dense(env, orc, storage, prec, lock):
+    torch, B, ctx = env
+    L = (4, 4, 4)
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=1)
+    w, d = _dense_window(orc, Hr, 4)
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1, storage=st)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=16, n_p=60, eps=1e-9, lock=lock,
+                         precision=B.PREC_C128 if prec == "c128" else B.PREC_C64, seed=3)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    want = w[np.abs(w) <= d]
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0, stats
+    assert ev.size == want.size == 4
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    # residuals recomputed by the reference from the returned vectors
+    r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
+    assert r.max() <= 1.05e-9
+    assert np.abs(V.conj().T @ V - np.eye(4)).max() < 1e-9
