@@ -3,16 +3,22 @@ eigenpairs (residual < 1e-9) on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload ti_64x64x32]
                     [--storage sell|stencil] [--precision c128|c64]
+                    [--kernel-only] [--no-cpu-baseline]
 
-A step is one complete ChebFD solve (Sec. 3.1 steps 1-8: bounds, filter
-coefficients, random block, N_p fused filter launches per iteration,
+A step is one complete ChebFD solve (Sec. 3.1 steps 1-8: spectral bounds,
+filter coefficients, random block, N_p fused filter launches per iteration,
 orthogonalisation, Rayleigh-Ritz, residuals, locking, restart) on the
 synthetic topological-insulator lattice, with the matrix and all blocks
-resident in HBM.  Prints one JSON line.
+resident in HBM when the timed region starts.  `value` is the algorithmic
+filter traffic of the whole solve (per fused launch: the matrix once, u read
+once, w and x read and written) divided by the solve's wall time.  The
+`roofline` object times the fused kernel alone with HIP events on the
+library's stream.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,24 +33,41 @@ import numpy as np  # noqa: E402
 import chebfd_inputs as inp  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h"],
+                  "stencil": ["kernels_stencil.hip", "pack.h"]}
 
 
-def vmin_bytes(nnz, n, n_b, s_d, s_i=4, stencil_site_bytes=0):
-    """Minimum bytes of one fused step (Sec. 4.2): the matrix once (values and
-    indices), u read once, w and x read and written."""
-    mat = nnz * (s_d + s_i) if not stencil_site_bytes else stencil_site_bytes
-    return mat + 5 * n * n_b * s_d
+def source_sha(storage):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[storage]:
+        with open(os.path.join(ROOT, "paper_1510_04895_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def step_flops(n, n_b, nnz_row):
-    """Flops of one step with the paper's complex counting (Sec. 4.2):
-    N_nzr (F_a + F_m) + ceil(9 F_a/2) + ceil(11 F_m/2) per row and vector."""
+    """Flops of one fused step with the paper's complex counting (Sec. 4.2):
+    N_nzr (F_a + F_m) + ceil(9 F_a/2) + ceil(11 F_m/2) per row and vector,
+    F_a = 2, F_m = 6."""
     return n * n_b * (nnz_row * 8 + 42)
 
 
+def measured_traffic(storage, precision, workload):
+    """HBM bytes per fused launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{storage}_{precision}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != source_sha(storage):
+        return None
+    return t
+
+
 def cpu_baseline(workload, n_steps=3):
-    """The CPU reference's filter step (plain CSR, OpenMP static) on the
-    same lattice and block width, timed on the host cores."""
+    """The CPU reference's filter (plain CSR, OpenMP static) on the same
+    lattice and block width, timed on the host cores."""
     import oracle
     w = inp.WORKLOADS[workload]
     L = w["L"]
@@ -52,16 +75,16 @@ def cpu_baseline(workload, n_steps=3):
     a, b = oracle.gershgorin(H)
     n_s = w["n_s"]
     X = inp.random_block(H.n, n_s, seed=1)
-    gam = oracle.gamma(-0.1, 0.1, a, b, n_steps)
+    gam = oracle.gamma(-w["delta"], w["delta"], a, b, n_steps)
     t0 = time.perf_counter()
     oracle.filter_block(H, a, b, gam, X)
     dt = time.perf_counter() - t0
-    vb = vmin_bytes(H.nnz, H.n, n_s, 16)
+    vb = H.nnz * 20 + 5 * H.n * n_s * 16
     return dict(value=round(n_steps * vb / dt / 1e9, 3), unit="GB/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=f"{n_steps} filter steps (Fig. fig:ChebFD, first two fused as in the "
-                       f"reference) on the full {L[0]}x{L[1]}x{L[2]} lattice, n_s={n_s}, c128, "
-                       f"{dt:.1f} s")
+                sample=f"filter of degree {n_steps} ({n_steps} recurrence steps of Fig. "
+                       f"fig:ChebFD) on the full {L[0]}x{L[1]}x{L[2]} lattice, n_s={n_s}, c128, "
+                       f"{dt:.1f} s; same per-step byte count as the GPU figure")
 
 
 def main():
@@ -72,13 +95,15 @@ def main():
     ap.add_argument("--workload", default="ti_64x64x32")
     ap.add_argument("--storage", default="sell", choices=["sell", "stencil"])
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the bandwidth probe and the timed fused launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=200,
+    ap.add_argument("--kernel-steps", type=int, default=100,
                     help="fused launches timed with HIP events for the roofline figure")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "column-sharded design is described but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding across GPUs "
+              "is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -89,8 +114,17 @@ def main():
     n_s = w["n_s"]
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
-    st = B.STORAGE_SELL if args.storage == "sell" else B.STORAGE_STENCIL
     prec = B.PREC_C128 if args.precision == "c128" else B.PREC_C64
+    s_d = 16 if prec == B.PREC_C128 else 8
+
+    # attainable bandwidth (read-only reduction, copy, 3-read/2-write stream)
+    buf = torch.empty(4 * 2**30, dtype=torch.uint8, device="cuda")
+    probe = B.chebfd_bandwidth_probe(ctx, buf, reps=5)
+    del buf
+    torch.cuda.empty_cache()
+    print(f"# probe GB/s read {probe[0]:.0f} copy {probe[1]:.0f} 3r2w {probe[2]:.0f}", flush=True)
+
+    st = B.STORAGE_SELL if args.storage == "sell" else B.STORAGE_STENCIL
     t0 = time.perf_counter()
     H = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st,
                     sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
@@ -98,16 +132,15 @@ def main():
     info = H.info()
     n, nnz = info["n"], info["nnz"]
     a, b = info["g_lo"], info["g_hi"]
-    s_d = 16 if prec == B.PREC_C128 else 8
     mat_bytes = info["matrix_bytes_c128"] if prec == B.PREC_C128 else info["matrix_bytes_c64"]
+    vb = mat_bytes + 5 * n * n_s * s_d              # algorithmic bytes per fused launch
+    print(f"# matrix {args.storage} N={n} nnz={nnz} built in {t_build:.2f} s", flush=True)
 
-    # window and filter degree
+    # window and filter degree (linear DOS near the centre: delta'/delta =
+    # sqrt(N_S/N_T) - 1, Sec. 2.4; eta-minimising N_p, Sec. 2.3)
     delta = w["delta"]
-    n_p = w.get("n_p")
-    if n_p is None:
-        # linear DOS near the centre: delta'/delta = sqrt(N_S/N_T) - 1 (Sec. 2.4)
-        dp = delta * (math.sqrt(n_s / w["n_target"]) - 1.0)
-        n_p, _ = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
+    dp = delta * (math.sqrt(n_s / w["n_target"]) - 1.0)
+    n_p, eta = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
 
     # --- the fused kernel alone, timed with HIP events on the library stream
     dt = torch.complex128 if prec == B.PREC_C128 else torch.complex64
@@ -125,67 +158,68 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     t_launch = ev0.elapsed_time(ev1) / 1e3 / ks
-    vb = mat_bytes + 5 * n * n_s * s_d
     kern_gbs = vb / t_launch / 1e9
     del X, U, W
     torch.cuda.empty_cache()
+    print(f"# fused launch {t_launch * 1e6:.1f} us = {kern_gbs:.0f} GB/s", flush=True)
 
-    # --- whole solves
-    params = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p,
-                              kernel=w["kernel"], mu=w["mu"], eps=w["eps"], max_iter=40,
-                              precision=prec, lock=1, seed=w["seeds"][0], vectors=0)
-    for _ in range(args.warmup):
-        B.chebfd_solve(ctx, H, params)
-    torch.cuda.synchronize()
-    times, results = [], []
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, ev, rs, _, stats = B.chebfd_solve(ctx, H, params)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        results.append((rc, ev, rs, stats))
-    T = float(np.mean(times))
-    rc, ev, rs, stats = results[-1]
-    # algorithmic filter bytes of the whole solve / wall time of the solve
-    mvm = stats["n_mvm"]                         # sum over iterations of columns * n_p
-    solve_bytes = mvm / n_s * vb if n_s else 0.0
-    value = solve_bytes / T / 1e9
-    nnz_row = nnz / n
-    flops = step_flops(n, n_s, nnz_row)
+    traffic = measured_traffic(args.storage, args.precision, args.workload)
+    roof = {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kern_gbs / HBM_PEAK_GBS, 4),
+            "traffic": (int(traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None),
+            "algorithmic_bytes_per_launch": int(vb), "avg_launch_us": round(t_launch * 1e6, 2),
+            "frac_of_probe_3r2w": round(kern_gbs / probe[2], 4)}
     out = {
-        "metric": "fused Chebyshev SpMMV GB/s (whole solve); time to all window eigenpairs @res<1e-9",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(T * 1e3, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c128/f64" if prec == B.PREC_C128 else "c64/f32+f64 polish",
+        "metric": "fused Chebyshev SpMMV GB/s vs HBM peak; time to all window eigenpairs @res<1e-9",
+        "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == B.PREC_C128 else "f32 sweep + f64 polish",
         "data": "synthetic",
-        "config": {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n,
-                   "n_s": n_s, "n_p": n_p, "kernel": w["kernel"], "window": [-delta, delta],
-                   "storage": args.storage, "sell": [w.get("sell_C"), w.get("sell_sigma")]
-                   if args.storage == "sell" else None, "eps": w["eps"]},
-        "time_to_solution_s": round(T, 4),
-        "eigenpairs_found": int(len(ev)),
-        "max_residual": float(rs.max()) if len(rs) else None,
-        "status": int(rc),
-        "solve_stats": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()},
-        "kernel_gbs": round(kern_gbs, 1),
-        "kernel_tflops": round(flops / t_launch / 1e12, 3),
-        "matrix_build_s": round(t_build, 2),
-        "roofline": {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(kern_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "per_launch_bytes": int(vb),
-                     "avg_launch_us": round(t_launch * 1e6, 2)},
     }
+    cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "n_s": n_s,
+           "n_p": n_p, "eta": round(eta, 2), "kernel": w["kernel"], "window": [-delta, delta],
+           "storage": args.storage,
+           "sell_C_sigma": [w.get("sell_C"), w.get("sell_sigma")] if args.storage == "sell" else None,
+           "eps": w["eps"]}
+
+    if args.kernel_only:
+        out.update({"value": round(kern_gbs, 2), "steps": 0, "warmup": 0,
+                    "ms_per_step": round(t_launch * 1e3, 4), "config": cfg,
+                    "note": "kernel only: value is the fused launch's algorithmic GB/s"})
+    else:
+        params = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p,
+                                  kernel=w["kernel"], mu=w["mu"], eps=w["eps"], max_iter=60,
+                                  precision=prec, lock=1, seed=w["seeds"][0], vectors=0)
+        for _ in range(args.warmup):
+            B.chebfd_solve(ctx, H, params)
+        torch.cuda.synchronize()
+        times, res = [], None
+        for k in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = B.chebfd_solve(ctx, H, params)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            print(f"# solve {k}: {times[-1]:.3f} s, {len(res[1])} pairs", flush=True)
+        T = float(np.mean(times))
+        rc, ev, rs, _, stats = res
+        solve_bytes = stats["n_mvm"] / n_s * vb     # sum over launches of algorithmic bytes
+        nnz_row = nnz / n
+        out.update({
+            "value": round(solve_bytes / T / 1e9, 2), "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(T * 1e3, 2), "config": cfg,
+            "time_to_solution_s": round(T, 4), "eigenpairs_found": int(len(ev)),
+            "max_residual": float(rs.max()) if len(rs) else None, "status": int(rc),
+            "solve_stats": {k: (round(v, 4) if isinstance(v, float) else v)
+                            for k, v in stats.items()},
+            "fused_kernel_tflops": round(step_flops(n, n_s, nnz_row) / t_launch / 1e12, 3),
+        })
+    out["roofline"] = roof
+    out["bandwidth_probe_gbs"] = {"read_only": round(probe[0], 1), "copy": round(probe[1], 1),
+                                  "stream_3r2w": round(probe[2], 1)}
+    out["matrix_build_s"] = round(t_build, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

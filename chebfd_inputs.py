@@ -20,7 +20,7 @@ WORKLOADS = {
                      kernel="lanczos", mu=2.0, eps=1e-9, n_target=16),
     # the FP64 throughput configuration
     "ti_64x64x32": dict(L=(64, 64, 32), pbc=3, V=1.0, seeds=(1,), n_s=256, kernel="lanczos",
-                        mu=2.0, eps=1e-9, n_target=64, delta=0.25, sell_C=32, sell_sigma=256),
+                        mu=2.0, eps=1e-9, n_target=64, delta=0.2072, sell_C=32, sell_sigma=256),
     # precision form
     "ti_128x128x64": dict(L=(128, 128, 64), pbc=3, V=1.0, seeds=(1,), n_s=256,
                           kernel="lanczos", mu=2.0, eps=1e-9, n_target=100),

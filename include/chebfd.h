@@ -232,12 +232,13 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  * Errors: INVALID_ARG for an unknown key or value. */
 int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value);
 
-/* Attainable HBM bandwidth (the read-only reduction benchmark of Sec. 4.1,
- * plus a copy): reads `bytes` of the device buffer `buf` (caller-owned,
- * 16-byte aligned, contents ignored, its second half overwritten by the
- * copy) `reps` times.  Outputs GB/s (10^9 bytes/s).  Synchronises. */
-int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps,
-                           double *read_gbs, double *copy_gbs);
+/* Attainable HBM bandwidth: gbs[0] the read-only reduction benchmark of
+ * Sec. 4.1, gbs[1] a plain copy (bytes read + written), gbs[2] the fused
+ * step's streams without the gather (read three blocks, write two:
+ * w = 2u - w, x = x + w/2).  Each runs `reps` times over the caller-owned
+ * device buffer `buf` (`bytes` long, 16-byte aligned, contents overwritten).
+ * GB/s = 10^9 bytes/s.  Synchronises. */
+int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs);
 
 /* Hermitian eigen-decomposition of a small dense matrix on the host
  * (Householder tridiagonalisation + implicit QL): A (n x n complex128,

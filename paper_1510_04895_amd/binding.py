@@ -84,7 +84,7 @@ def lib():
         "chebfd_kpm_moments": (i32, [vp, vp, i32, i32, i32, u64, dbl, dbl, vp]),
         "chebfd_host_eigh": (i32, [i32, vp, vp]),
         "chebfd_set_tuning": (i32, [vp, C.c_char_p, i32]),
-        "chebfd_bandwidth_probe": (i32, [vp, vp, i64, i32, vp, vp]),
+        "chebfd_bandwidth_probe": (i32, [vp, vp, i64, i32, vp]),
         "chebfd_params_default": (i32, [vp]),
         "chebfd_solve_workspace_size": (i32, [vp, vp, vp]),
         "chebfd_solve": (i32, [vp, vp, vp, vp, i64, pp]),
@@ -303,10 +303,11 @@ def chebfd_set_tuning(ctx, key, value):
 
 
 def chebfd_bandwidth_probe(ctx, buf, reps=10):
-    r, c = C.c_double(), C.c_double()
+    """(read-only, copy, 3-read/2-write stream) GB/s over the device buffer."""
+    out = np.zeros(3)
     nbytes = buf.numel() * buf.element_size()
-    _check(lib().chebfd_bandwidth_probe(ctx.h, _ptr(buf), nbytes, reps, C.byref(r), C.byref(c)))
-    return r.value, c.value
+    _check(lib().chebfd_bandwidth_probe(ctx.h, _ptr(buf), nbytes, reps, _ptr(out)))
+    return tuple(float(v) for v in out)
 
 
 def chebfd_kpm_moments(ctx, H, n_vec, n_mom, seed, a, b, precision=PREC_C64):

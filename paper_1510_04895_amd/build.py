@@ -23,6 +23,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         # host code: AVX2/FMA (x86-64-v3) for the small dense eigenproblems
+         "-Xarch_host", "-mavx2", "-Xarch_host", "-mfma",
+         # plain complex products (no inf/nan rescue calls) in host code
+         "-Xarch_host", "-fcx-limited-range",
          "-I" + os.path.join(ROOT, "include")]
 
 

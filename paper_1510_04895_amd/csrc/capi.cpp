@@ -348,13 +348,12 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     return CHEBFD_OK;
 }
 
-int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *read_gbs,
-                           double *copy_gbs)
+int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs)
 {
-    if (!ctx || !buf || !read_gbs || !copy_gbs || bytes < 4096 || reps < 1 || ((uintptr_t)buf & 15))
+    if (!ctx || !buf || !gbs || bytes < 4096 || reps < 1 || ((uintptr_t)buf & 15))
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_bandwidth_probe: invalid arguments");
     CHEBFD_HIP(hipSetDevice(ctx->device));
-    return launch_bandwidth_probe(ctx, buf, bytes, reps, read_gbs, copy_gbs);
+    return launch_bandwidth_probe(ctx, buf, bytes, reps, gbs);
 }
 
 int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, int n_vec,

@@ -74,8 +74,10 @@ void tridiagonalise(int n, std::vector<cd> &A, std::vector<cd> &Q)
 }
 
 // Implicit QL on the real symmetric tridiagonal (d, e), e[i] coupling i and
-// i+1; Z (n x n, row-major) accumulates the rotations.
-int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Z)
+// i+1.  The rotations are accumulated into Zt, the transpose of the
+// eigenvector matrix (row i of Zt = eigenvector column i), so each rotation
+// updates two contiguous rows.
+int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt)
 {
     const double eps = 2.220446049250313e-16;
     e.resize(n);
@@ -113,11 +115,11 @@ int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::v
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - bb;
+                double *zi = &Zt[(size_t)i * n], *zj = &Zt[(size_t)(i + 1) * n];
                 for (int k = 0; k < n; ++k) {
-                    double *zr = &Z[(size_t)k * n];
-                    const double zf = zr[i + 1];
-                    zr[i + 1] = s * zr[i] + c * zf;
-                    zr[i] = c * zr[i] - s * zf;
+                    const double zf = zj[k];
+                    zj[k] = s * zi[k] + c * zf;
+                    zi[k] = c * zi[k] - s * zf;
                 }
             }
             if (split) continue;
@@ -156,26 +158,70 @@ int herm_eig(int n, std::vector<double> &Ain, std::vector<double> &w)
         e[i] = a;
         delta[i + 1] = a > 0.0 ? delta[i] * (sub / a) : delta[i];
     }
-    std::vector<double> Z((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
-    if (tridiagonal_ql(n, d, e, Z) != 0) return -1;
+    std::vector<double> Zt((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
+    if (tridiagonal_ql(n, d, e, Zt) != 0) return -1;
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
-    // V = Q D Z, columns in ascending eigenvalue order
+    // V = Q D Z, columns in ascending eigenvalue order:
+    // V[r][j] = sum_i (Q D)[r][i] Zt[ord j][i]
     std::vector<cd> QD((size_t)n * n);
     for (int r = 0; r < n; ++r)
         for (int i = 0; i < n; ++i) QD[(size_t)r * n + i] = Q[(size_t)r * n + i] * delta[i];
     for (int j = 0; j < n; ++j) w[j] = d[ord[j]];
     for (int r = 0; r < n; ++r) {
+        const cd *qr = &QD[(size_t)r * n];
         for (int j = 0; j < n; ++j) {
-            const int c = ord[j];
-            cd s = 0.0;
-            for (int i = 0; i < n; ++i) s += QD[(size_t)r * n + i] * Z[(size_t)i * n + c];
-            Ain[2 * ((size_t)r * n + j)] = s.real();
-            Ain[2 * ((size_t)r * n + j) + 1] = s.imag();
+            const double *z = &Zt[(size_t)ord[j] * n];
+            double sr = 0.0, si = 0.0;
+            for (int i = 0; i < n; ++i) {
+                sr += qr[i].real() * z[i];
+                si += qr[i].imag() * z[i];
+            }
+            Ain[2 * ((size_t)r * n + j)] = sr;
+            Ain[2 * ((size_t)r * n + j) + 1] = si;
         }
     }
+    return 0;
+}
+
+// T = L^{-H} for the Cholesky factor S = L L^H of a Hermitian positive
+// definite S (n x n, interleaved complex, row-major); T is upper
+// triangular, so that (Y T)^H (Y T) = I for S = Y^H Y.  Returns -1 when S is
+// not numerically positive definite.
+int chol_inv_factor(int n, const std::vector<double> &Sin, std::vector<double> &Tout)
+{
+    std::vector<cd> L((size_t)n * n, cd(0.0));
+    for (int j = 0; j < n; ++j) {
+        double djj = Sin[2 * ((size_t)j * n + j)];
+        for (int k = 0; k < j; ++k) djj -= std::norm(L[(size_t)j * n + k]);
+        if (!(djj > 0.0)) return -1;
+        const double ljj = std::sqrt(djj);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cd sij(Sin[2 * ((size_t)i * n + j)], Sin[2 * ((size_t)i * n + j) + 1]);
+            for (int k = 0; k < j; ++k) sij -= L[(size_t)i * n + k] * std::conj(L[(size_t)j * n + k]);
+            L[(size_t)i * n + j] = sij / ljj;
+        }
+    }
+    // M = L^{-1} (lower) by forward substitution, column by column
+    std::vector<cd> M((size_t)n * n, cd(0.0));
+    for (int c = 0; c < n; ++c) {
+        M[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+        for (int i = c + 1; i < n; ++i) {
+            cd s = 0.0;
+            for (int k = c; k < i; ++k) s += L[(size_t)i * n + k] * M[(size_t)k * n + c];
+            M[(size_t)i * n + c] = -s / L[(size_t)i * n + i];
+        }
+    }
+    Tout.assign((size_t)2 * n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd t = std::conj(M[(size_t)j * n + i]);   // (L^{-1})^H
+            Tout[2 * ((size_t)i * n + j)] = t.real();
+            Tout[2 * ((size_t)i * n + j) + 1] = t.imag();
+        }
     return 0;
 }
 

@@ -127,8 +127,7 @@ int launch_convert(chebfd_ctx *ctx, int prec_in, const void *X, int prec_out, vo
                    int64_t n, int64_t n_s, int64_t ld_in, int64_t ld_out);
 int launch_phase_block(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s,
                        int64_t ld, uint64_t seed, uint64_t stream);
-int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps,
-                           double *read_gbs, double *copy_gbs);
+int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs);
 int launch_expand_T(chebfd_ctx *ctx, const double *T, int64_t k, int64_t m, double *Tr);
 int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, void *dst,
                        int64_t ldd, int64_t d0, const int32_t *idx_dev, int64_t n, int64_t m);
@@ -146,6 +145,7 @@ void quality(const double *gamma, int n_p, double a, double b, double t_lo, doub
              double s_lo, double s_hi, double *sigma, double *eta);
 int herm_eig(int n, std::vector<double> &A /* 2*n*n, overwritten by vectors */,
              std::vector<double> &w);
+int chol_inv_factor(int n, const std::vector<double> &S, std::vector<double> &T);
 
 // host-side random numbers (same definition as the device kernels)
 uint64_t mix64(uint64_t z);

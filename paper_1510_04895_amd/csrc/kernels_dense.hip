@@ -296,8 +296,23 @@ __global__ __launch_bounds__(256) void k_copy16(const pd2 *__restrict__ src, pd2
                                                 int64_t n16)
 {
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+// The fused step's streams without the gather: read u, w, x; write
+// w = 2u - w and x = x + w (three reads, two writes per element).
+__global__ __launch_bounds__(256) void k_stream_3r2w(const pd2 *__restrict__ u, pd2 *w, pd2 *x,
+                                                     int64_t n16)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+        const pd2 a = u[i];
+        const pd2 b = __builtin_nontemporal_load(w + i);
+        const pd2 c = __builtin_nontemporal_load(x + i);
+        const pd2 wn = 2.0 * a - b;
+        __builtin_nontemporal_store(wn, w + i);
+        __builtin_nontemporal_store(c + 0.5 * wn, x + i);
+    }
 }
 
 // Real (2k x 2m) expansion of a complex (k x m) matrix for A T products.
@@ -452,39 +467,36 @@ int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, 
     return CHEBFD_OK;
 }
 
-int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps,
-                           double *read_gbs, double *copy_gbs)
+int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs)
 {
     const int64_t n16 = bytes / 16;
-    const int64_t half = n16 / 2;
     const unsigned grid = (unsigned)(ctx->num_cu * 16);
     int rc = ensure_scratch(ctx, (size_t)grid * sizeof(double));
     if (rc) return rc;
     double *part = (double *)ctx->scratch;
+    pd2 *p = (pd2 *)buf;
+    const int64_t half = n16 / 2, third = n16 / 3;
     hipEvent_t e0, e1;
     CHEBFD_HIP(hipEventCreate(&e0));
     CHEBFD_HIP(hipEventCreate(&e1));
-    float ms = 0.0f;
-    // warm-up, then timed repetitions
-    hipLaunchKernelGGL(k_read_reduce, dim3(grid), dim3(256), 0, ctx->stream, (const pd2 *)buf, n16, part);
-    CHEBFD_HIP(hipEventRecord(e0, ctx->stream));
-    for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_read_reduce, dim3(grid), dim3(256), 0, ctx->stream, (const pd2 *)buf,
-                           n16, part);
-    CHEBFD_HIP(hipEventRecord(e1, ctx->stream));
-    CHEBFD_HIP(hipEventSynchronize(e1));
-    CHEBFD_HIP(hipEventElapsedTime(&ms, e0, e1));
-    *read_gbs = (double)n16 * 16 * reps / (ms * 1e-3) / 1e9;
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, ctx->stream, (const pd2 *)buf,
-                       (pd2 *)buf + half, half);
-    CHEBFD_HIP(hipEventRecord(e0, ctx->stream));
-    for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, ctx->stream, (const pd2 *)buf,
-                           (pd2 *)buf + half, half);
-    CHEBFD_HIP(hipEventRecord(e1, ctx->stream));
-    CHEBFD_HIP(hipEventSynchronize(e1));
-    CHEBFD_HIP(hipEventElapsedTime(&ms, e0, e1));
-    *copy_gbs = (double)half * 32 * reps / (ms * 1e-3) / 1e9;
+    for (int which = 0; which < 3; ++which) {
+        float ms = 0.0f;
+        for (int r = -1; r < reps; ++r) {   // r = -1: warm-up
+            if (r == 0) CHEBFD_HIP(hipEventRecord(e0, ctx->stream));
+            if (which == 0)
+                hipLaunchKernelGGL(k_read_reduce, dim3(grid), dim3(256), 0, ctx->stream, p, n16, part);
+            else if (which == 1)
+                hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, ctx->stream, p, p + half, half);
+            else
+                hipLaunchKernelGGL(k_stream_3r2w, dim3(grid), dim3(256), 0, ctx->stream, p,
+                                   p + third, p + 2 * third, third);
+        }
+        CHEBFD_HIP(hipEventRecord(e1, ctx->stream));
+        CHEBFD_HIP(hipEventSynchronize(e1));
+        CHEBFD_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double moved = which == 0 ? n16 * 16.0 : (which == 1 ? half * 32.0 : third * 80.0);
+        gbs[which] = moved * reps / (ms * 1e-3) / 1e9;
+    }
     CHEBFD_HIP(hipEventDestroy(e0));
     CHEBFD_HIP(hipEventDestroy(e1));
     CHEBFD_CHECK_LAUNCH();

@@ -8,8 +8,8 @@
 //   MODE_APPLY : w = s_h H u + s_u u
 //   MODE_SECOND: w = s_h H u + s_u u - x ;  x = g0 x + g1 u + g2 w
 //   MODE_STEP  : w = s_h H u + s_u u - w ;  x = x + g0 w
-// Work decomposition: a workgroup of 256 lanes owns one SELL chunk (C rows)
-// and one column slab of LPR*NB complex columns.  LPR lanes share a row, so a
+// Work decomposition: a workgroup of 256 lanes owns one SELL chunk (C <= 64
+// rows) and one column slab of LPR*NB complex columns.  LPR lanes share a row, so a
 // wave covers 64/LPR rows; each lane owns NB consecutive complex columns and
 // moves them with one 16-byte access.  The gathered block u is only read;
 // w and x are read and written only at the workgroup's own rows, so the
@@ -24,7 +24,40 @@
 namespace chebfd {
 namespace {
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT>
+// Accumulates one row of the sparse product from (index, value) pairs
+// served by `src(j)`, GB gathers in flight at a time.
+template <typename T, int NB, int GB, typename Src>
+__device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld, int64_t c0,
+                                            int cnt, int len, Src src, T (&ar)[NB], T (&ai)[NB])
+{
+#pragma unroll
+    for (int e = 0; e < NB; ++e) ar[e] = ai[e] = T(0);
+    for (int j = 0; j < len; j += GB) {
+        Pack<T, NB> g[GB];
+        T hr[GB], hi[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+            if (j + i < len) {
+                int ci;
+                src(j + i, ci, hr[i], hi[i]);
+                g[i] = load_pack_n<T, NB>(u + 2 * ((int64_t)ci * ld + c0), cnt);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+            if (j + i >= len) break;
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                ar[e] += hr[i] * g[i].re[e] - hi[i] * g[i].im[e];
+                ai[e] += hr[i] * g[i].im[e] + hi[i] * g[i].re[e];
+            }
+        }
+    }
+}
+
+constexpr int LDS_ENTRIES = 1024;   // index/value pairs of one chunk staged in LDS
+
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED>
 __global__ __launch_bounds__(256) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
@@ -35,6 +68,9 @@ __global__ __launch_bounds__(256) void k_step_sell(
     constexpr int RPW = 64 / LPR;        // rows per wave
     constexpr int RPP = 4 * RPW;         // rows per pass of the workgroup
     constexpr int SW = LPR * NB;         // slab width in complex columns
+    constexpr int GB = 8;                // gathers in flight per row
+    __shared__ int32_t s_col[LDS_ENTRIES];
+    __shared__ T s_val[2 * LDS_ENTRIES];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int rsub = lane / LPR, cl = lane % LPR;
@@ -54,52 +90,46 @@ __global__ __launch_bounds__(256) void k_step_sell(
     const bool active = c0 < n_s;
     const int len = chunk_len[chunk];
     const int64_t base = chunk_ptr[chunk];
+    // chunks that fit are staged in LDS with coalesced loads, so the gathers
+    // of a row never wait on an index load; wider chunks read the stream
+    // directly
+    constexpr bool staged = STAGED;
+    if (staged) {
+        for (int t = tid; t < len * C; t += 256) {
+            s_col[t] = col[base + t];
+            s_val[2 * t] = val[2 * (base + t)];
+            s_val[2 * t + 1] = val[2 * (base + t) + 1];
+        }
+        __syncthreads();
+    }
 
     double m0[NB], m1[NB], m2[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
 
     for (int r = wave * RPW + rsub; r < C; r += RPP) {
-        const int64_t slot = chunk * C + r;
-        const int row = perm[slot];
+        const int row = perm[chunk * C + r];
         if (row < 0 || !active) continue;
         T ar[NB], ai[NB];
-#pragma unroll
-        for (int e = 0; e < NB; ++e) ar[e] = ai[e] = T(0);
-        const int64_t eb = base + r;
-        int j = 0;
-        for (; j + 4 <= len; j += 4) {
-            int cidx[4];
-            T hr[4], hi[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t e = eb + (int64_t)(j + q) * C;
-                cidx[q] = col[e];
-                hr[q] = val[2 * e];
-                hi[q] = val[2 * e + 1];
-            }
-            Pack<T, NB> g[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                g[q] = load_pack_n<T, NB>(u + 2 * ((int64_t)cidx[q] * ld + c0), cnt);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int e = 0; e < NB; ++e) {
-                    ar[e] += hr[q] * g[q].re[e] - hi[q] * g[q].im[e];
-                    ai[e] += hr[q] * g[q].im[e] + hi[q] * g[q].re[e];
-                }
-        }
-        for (; j < len; ++j) {
-            const int64_t e = eb + (int64_t)j * C;
-            const int ci = col[e];
-            const T hr = val[2 * e], hi = val[2 * e + 1];
-            Pack<T, NB> g = load_pack_n<T, NB>(u + 2 * ((int64_t)ci * ld + c0), cnt);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                ar[q] += hr * g.re[q] - hi * g.im[q];
-                ai[q] += hr * g.im[q] + hi * g.re[q];
-            }
+        if (staged) {
+            row_product<T, NB, GB>(u, ld, c0, cnt, len,
+                                   [&](int j, int &ci, T &hr, T &hi) {
+                                       const int t = j * C + r;
+                                       ci = s_col[t];
+                                       hr = s_val[2 * t];
+                                       hi = s_val[2 * t + 1];
+                                   },
+                                   ar, ai);
+        } else {
+            const int64_t eb = base + r;
+            row_product<T, NB, GB>(u, ld, c0, cnt, len,
+                                   [&](int j, int &ci, T &hr, T &hi) {
+                                       const int64_t e = eb + (int64_t)j * C;
+                                       ci = col[e];
+                                       hr = val[2 * e];
+                                       hi = val[2 * e + 1];
+                                   },
+                                   ar, ai);
         }
         const int64_t off = 2 * ((int64_t)row * ld + c0);
         const Pack<T, NB> uo = load_pack_n<T, NB>(u + off, cnt);
@@ -181,16 +211,15 @@ __global__ __launch_bounds__(256) void k_step_sell(
 #pragma unroll
             for (int e = 0; e < NB; ++e) {
                 if (e >= cnt) break;
-                double s0 = red[0][lane][3 * e] + red[1][lane][3 * e] + red[2][lane][3 * e] +
-                            red[3][lane][3 * e];
-                double s1 = red[0][lane][3 * e + 1] + red[1][lane][3 * e + 1] +
-                            red[2][lane][3 * e + 1] + red[3][lane][3 * e + 1];
-                double s2 = red[0][lane][3 * e + 2] + red[1][lane][3 * e + 2] +
-                            red[2][lane][3 * e + 2] + red[3][lane][3 * e + 2];
+                double sq[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    sq[q] = red[0][lane][3 * e + q] + red[1][lane][3 * e + q] +
+                            red[2][lane][3 * e + q] + red[3][lane][3 * e + q];
                 double *p = partials + 3 * (chunk * n_s + c0 + e);
-                p[0] = s0;
-                p[1] = s1;
-                p[2] = s2;
+                p[0] = sq[0];
+                p[1] = sq[1];
+                p[2] = sq[2];
             }
         }
     }
@@ -242,11 +271,19 @@ int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
     const int64_t nslab = (a.n_s + SW - 1) / SW;
     const int64_t grid = S.nchunks * nslab;
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT>), dim3((unsigned)grid), dim3(256),
-                       0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col, val, S.C,
-                       S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y,
-                       a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials,
-                       ctx->tune_order, nslab);
+    // every chunk fits in LDS -> staged variant, else direct index stream
+    if ((int64_t)S.max_len * S.C <= LDS_ENTRIES)
+        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true>), dim3((unsigned)grid),
+                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
+                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
+                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
+                           a.partials, ctx->tune_order, nslab);
+    else
+        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, false>), dim3((unsigned)grid),
+                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
+                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
+                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
+                           a.partials, ctx->tune_order, nslab);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }

@@ -178,19 +178,35 @@ struct Solver {
                     S[2 * ((size_t)i * k + j)] *= d[i] * d[j];
                     S[2 * ((size_t)i * k + j) + 1] *= d[i] * d[j];
                 }
-            if (herm_eig(k, S, w) != 0) return fail(CHEBFD_ERR_NONFINITE, "SVQB eigensolver failed");
-            const double tmax = w[k - 1];
-            // T = D U Theta^{-1/2}, kept directions, largest first
-            T.assign((size_t)2 * k * k, 0.0);
-            int keep = 0;
-            for (int j = k - 1; j >= 0; --j) {
-                if (!(w[j] > 1e-12 * tmax)) continue;
-                const double f = 1.0 / std::sqrt(w[j]);
-                for (int i = 0; i < k; ++i) {
-                    T[2 * ((size_t)i * k + keep)] = d[i] * S[2 * ((size_t)i * k + j)] * f;
-                    T[2 * ((size_t)i * k + keep) + 1] = d[i] * S[2 * ((size_t)i * k + j) + 1] * f;
+            // after a clean rank-revealing pass the block is close to
+            // orthonormal: the second pass uses the Cholesky factor of the
+            // scaled Gram (T = D L^{-H}), falling back to the eigenvalue
+            // form if the factorisation breaks down
+            int keep = k;
+            bool done = false;
+            if (clean >= 1 && chol_inv_factor(k, S, T) == 0) {
+                for (int i = 0; i < k; ++i)
+                    for (int j = 0; j < k; ++j) {
+                        T[2 * ((size_t)i * k + j)] *= d[i];
+                        T[2 * ((size_t)i * k + j) + 1] *= d[i];
+                    }
+                done = true;
+            }
+            if (!done) {
+                if (herm_eig(k, S, w) != 0) return fail(CHEBFD_ERR_NONFINITE, "SVQB eigensolver failed");
+                const double tmax = w[k - 1];
+                // T = D U Theta^{-1/2}, kept directions, largest first
+                T.assign((size_t)2 * k * k, 0.0);
+                keep = 0;
+                for (int j = k - 1; j >= 0; --j) {
+                    if (!(w[j] > 1e-12 * tmax)) continue;
+                    const double f = 1.0 / std::sqrt(w[j]);
+                    for (int i = 0; i < k; ++i) {
+                        T[2 * ((size_t)i * k + keep)] = d[i] * S[2 * ((size_t)i * k + j)] * f;
+                        T[2 * ((size_t)i * k + keep) + 1] = d[i] * S[2 * ((size_t)i * k + j) + 1] * f;
+                    }
+                    ++keep;
                 }
-                ++keep;
             }
             if ((rc = upload_T(T, k, k))) return rc;
             if ((rc = launch_block_times(ctx, prec, *X, ns, n, k, dTr, k, prec, *Y, ns, 0)))
