@@ -227,7 +227,8 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *                 0 = default (32; 16 for blocks of at most 16 packs);
  *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
  *   "order"       0 (default) = workgroups ordered column-slab major,
- *                 1 = row-chunk major.
+ *                 1 = row-chunk major;
+ *   "gathers"     SELL only: gathered rows in flight per row, 8 (default) or 16.
  * Results are identical for every setting; only speed changes.
  * Errors: INVALID_ARG for an unknown key or value. */
 int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value);

@@ -344,6 +344,7 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     if (k == "lanes" && (value == 0 || value == 16 || value == 32 || value == 64)) ctx->tune_lpr = value;
     else if (k == "nontemporal" && (value == 0 || value == 1)) ctx->tune_nt = value;
     else if (k == "order" && (value == 0 || value == 1)) ctx->tune_order = value;
+    else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");
     return CHEBFD_OK;
 }

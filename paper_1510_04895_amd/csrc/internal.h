@@ -72,6 +72,7 @@ struct chebfd_ctx {
     int tune_lpr = 0;     // lanes per row/site: 0 = default (32), 16, 32, 64
     int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
     int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
+    int tune_gathers = 8; // gathers in flight per row (SELL): 8 or 16
 };
 
 struct chebfd_matrix {

@@ -108,6 +108,17 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
         const int yy = (int)(rem / Lx);
         const int x = (int)(rem - (int64_t)yy * Lx);
         const Site<T, NB> uo = load_site<T, NB>(u, site, ld, c0, cnt);
+        // streamed operands of the four output rows, issued before the
+        // neighbour loads they do not depend on
+        Site<T, NB> wo, yo;
+        if (MODE == MODE_SECOND || MODE == MODE_STEP)
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                wo.o[o] = load_pack_n<T, NB, NT>(wold + 2 * ((4 * site + o) * ld + c0), cnt);
+        if (MODE == MODE_STEP)
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                yo.o[o] = load_pack_n<T, NB, NT>(y + 2 * ((4 * site + o) * ld + c0), cnt);
         const T vn = pot[site];
         Pack<T, NB> acc[4];
 #pragma unroll
@@ -184,7 +195,7 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                     }
                 }
             } else if (MODE == MODE_SECOND) {
-                const Pack<T, NB> xo = load_pack_n<T, NB, NT>(wold + off, cnt);
+                const Pack<T, NB> xo = wo.o[o];
                 Pack<T, NB> xn;
 #pragma unroll
                 for (int e = 0; e < NB; ++e) {
@@ -203,12 +214,11 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                     }
                 }
             } else {
-                const Pack<T, NB> wo = load_pack_n<T, NB, NT>(wold + off, cnt);
-                Pack<T, NB> yv = load_pack_n<T, NB, NT>(y + off, cnt);
+                Pack<T, NB> yv = yo.o[o];
 #pragma unroll
                 for (int e = 0; e < NB; ++e) {
-                    w.re[e] -= wo.re[e];
-                    w.im[e] -= wo.im[e];
+                    w.re[e] -= wo.o[o].re[e];
+                    w.im[e] -= wo.o[o].im[e];
                     yv.re[e] += g0 * w.re[e];
                     yv.im[e] += g0 * w.im[e];
                 }
@@ -242,7 +252,7 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
         if (wave == 0 && lane < LPS && c0 < n_s) {
 #pragma unroll
             for (int e = 0; e < NB; ++e) {
-                if (e >= cnt) break;
+                if (e >= cnt) continue;
                 double s[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q)

@@ -45,11 +45,12 @@ __device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld,
         }
 #pragma unroll
         for (int i = 0; i < GB; ++i) {
-            if (j + i >= len) break;
+            if (j + i < len) {
 #pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                ar[e] += hr[i] * g[i].re[e] - hi[i] * g[i].im[e];
-                ai[e] += hr[i] * g[i].im[e] + hi[i] * g[i].re[e];
+                for (int e = 0; e < NB; ++e) {
+                    ar[e] += hr[i] * g[i].re[e] - hi[i] * g[i].im[e];
+                    ai[e] += hr[i] * g[i].im[e] + hi[i] * g[i].re[e];
+                }
             }
         }
     }
@@ -57,7 +58,7 @@ __device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld,
 
 constexpr int LDS_ENTRIES = 1024;   // index/value pairs of one chunk staged in LDS
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
 __global__ __launch_bounds__(256) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
@@ -68,7 +69,6 @@ __global__ __launch_bounds__(256) void k_step_sell(
     constexpr int RPW = 64 / LPR;        // rows per wave
     constexpr int RPP = 4 * RPW;         // rows per pass of the workgroup
     constexpr int SW = LPR * NB;         // slab width in complex columns
-    constexpr int GB = 8;                // gathers in flight per row
     __shared__ int32_t s_col[LDS_ENTRIES];
     __shared__ T s_val[2 * LDS_ENTRIES];
     const int tid = threadIdx.x;
@@ -110,6 +110,12 @@ __global__ __launch_bounds__(256) void k_step_sell(
     for (int r = wave * RPW + rsub; r < C; r += RPP) {
         const int row = perm[chunk * C + r];
         if (row < 0 || !active) continue;
+        // the row's own operands first: they do not depend on the product
+        const int64_t off = 2 * ((int64_t)row * ld + c0);
+        const Pack<T, NB> uo = load_pack_n<T, NB>(u + off, cnt);
+        Pack<T, NB> wo, yv;
+        if (MODE == MODE_SECOND || MODE == MODE_STEP) wo = load_pack_n<T, NB, NT>(wold + off, cnt);
+        if (MODE == MODE_STEP) yv = load_pack_n<T, NB, NT>(y + off, cnt);
         T ar[NB], ai[NB];
         if (staged) {
             row_product<T, NB, GB>(u, ld, c0, cnt, len,
@@ -131,8 +137,6 @@ __global__ __launch_bounds__(256) void k_step_sell(
                                    },
                                    ar, ai);
         }
-        const int64_t off = 2 * ((int64_t)row * ld + c0);
-        const Pack<T, NB> uo = load_pack_n<T, NB>(u + off, cnt);
         Pack<T, NB> w;
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(256) void k_step_sell(
                 }
             }
         } else if (MODE == MODE_SECOND) {
-            const Pack<T, NB> xo = load_pack_n<T, NB, NT>(wold + off, cnt);
+            const Pack<T, NB> xo = wo;
             Pack<T, NB> xn;
 #pragma unroll
             for (int e = 0; e < NB; ++e) {
@@ -170,8 +174,6 @@ __global__ __launch_bounds__(256) void k_step_sell(
                 }
             }
         } else {
-            const Pack<T, NB> wo = load_pack_n<T, NB, NT>(wold + off, cnt);
-            Pack<T, NB> yv = load_pack_n<T, NB, NT>(y + off, cnt);
 #pragma unroll
             for (int e = 0; e < NB; ++e) {
                 w.re[e] -= wo.re[e];
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(256) void k_step_sell(
         if (wave == 0 && lane < LPR && active) {
 #pragma unroll
             for (int e = 0; e < NB; ++e) {
-                if (e >= cnt) break;
+                if (e >= cnt) continue;
                 double sq[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -272,14 +274,20 @@ int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
     const int64_t grid = S.nchunks * nslab;
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
     // every chunk fits in LDS -> staged variant, else direct index stream
-    if ((int64_t)S.max_len * S.C <= LDS_ENTRIES)
-        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true>), dim3((unsigned)grid),
+    if ((int64_t)S.max_len * S.C <= LDS_ENTRIES && ctx->tune_gathers == 16)
+        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true, 16>), dim3((unsigned)grid),
+                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
+                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
+                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
+                           a.partials, ctx->tune_order, nslab);
+    else if ((int64_t)S.max_len * S.C <= LDS_ENTRIES)
+        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true, 8>), dim3((unsigned)grid),
                            dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
                            val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
                            (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
                            a.partials, ctx->tune_order, nslab);
     else
-        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, false>), dim3((unsigned)grid),
+        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, false, 8>), dim3((unsigned)grid),
                            dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
                            val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
                            (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
