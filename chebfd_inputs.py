@@ -96,3 +96,13 @@ def random_hermitian_csr(n: int, seed: int, min_row=1, max_row=24, diag_shift=0.
         vals.extend(rows[i][c] for c in cs)
         rowptr[i + 1] = len(cols)
     return rowptr, np.array(cols, np.int32), np.array(vals, np.complex128)
+
+
+def learned_sample(seed: int):
+    """Disorder strength W ~ U[0, 2] and relative window half-width
+    delta / S_w log-uniform in [1e-3, 5e-2] for one realisation of the
+    learned-form workload (32x32x16 lattice)."""
+    g = rng(1_000_003 * seed + 17)
+    W = float(g.uniform(0.0, 2.0))
+    rel = float(10 ** g.uniform(np.log10(1e-3), np.log10(5e-2)))
+    return W, rel

@@ -248,6 +248,87 @@ int chebfd_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, 
 int chebfd_host_eigh(int n, double *A, double *w);
 
 /* ------------------------------------------------------------------ */
+/* parameter choice from KPM moments, and the learned form            */
+/* ------------------------------------------------------------------ */
+
+/* Rule-based parameters from n_mom KPM moments mu (host, as returned by
+ * chebfd_kpm_moments, normalised by N R) of an N x N matrix with spectral
+ * interval [a, b] (Sec. 3.1 steps 1-3): the target count
+ * N_T = N sum_m g_m c_m mu_m (Eq. DOS:target; Jackson damping, window
+ * coefficients c_m of Eq. (W1)); N_S = max(16, ceil(ns_over_nt N_T)) rounded
+ * to even and capped at ns_max; the search margin delta' from
+ * N_S = N int_{I_S} rho (Eq. DOS:search), at least the KPM resolution
+ * (b - a)/n_mom; and N_p minimising eta (Sec. 2.3) for that configuration
+ * with the given kernel.  A positive *n_s on entry fixes N_S (the margin and
+ * N_p then follow from it).  *margin (may be NULL) receives delta'.  This is
+ * the fallback of the learned form. */
+int chebfd_dos_params(const double *mu, int n_mom, int64_t n, double a, double b, double lam_lo,
+                      double lam_hi, double ns_over_nt, int kernel, double mu_k, int ns_max,
+                      double *n_t_est, int *n_s, int *n_p, double *margin);
+
+/* Network inputs (n_mom + 2 floats, host): the moments followed by the window
+ * edges in scaled units alpha lambda + beta. */
+int chebfd_learned_features(const double *mu, int n_mom, double a, double b, double lam_lo,
+                            double lam_hi, float *features);
+
+/* Decodes network outputs (host, 2 + n_hat floats: log(N_p / np_ref),
+ * log(N_S / ns_ref), hat amplitudes a_j; the ratios are bounded to 8 either
+ * way and np_ref, ns_ref are the rule-based choice) into n_p, an even n_s in
+ * [16, ns_max], and, if gamma_corr is not NULL, corr_len multiplicative
+ * coefficient corrections corr_n = c_max tanh(sum_j a_j hat_j(n /
+ * (corr_len - 1))) with n_hat equidistant piecewise-linear hats on [0, 1] (a
+ * zero output reproduces the rule-based filter exactly). */
+int chebfd_learned_decode(const float *out, int np_ref, int ns_ref, int n_hat, double c_max,
+                          int ns_max, int *n_p, int *n_s, double *gamma_corr, int corr_len);
+
+/* Fits hat amplitudes (amp: n_hat doubles, host) that minimise a smoothed
+ * damping factor sigma (Sec. 2.3) of the corrected filter
+ * sum_n gamma_n (1 + c_max tanh(sum_j a_j hat_j(n/n_p))) T_n for target
+ * [t_lo, t_hi] and search interval [s_lo, s_hi] plus l2 |a|^2, by `iters`
+ * Adam steps with the analytic gradient; sigma_out receives the smoothed
+ * sigma reached.  Produces the correction targets the network is trained on. */
+int chebfd_fit_corrections(double a, double b, double t_lo, double t_hi, double s_lo, double s_hi,
+                           int n_p, int kernel, double mu_k, int n_hat, double c_max, int iters,
+                           double l2, double *amp, double *sigma_out);
+
+typedef struct chebfd_mlp chebfd_mlp;
+
+/* Fully connected network n_in -> n_hidden (tanh) -> n_hidden (tanh) -> n_out
+ * (linear) in FP32 on the device, Glorot-uniform weights from the counter
+ * generator (stream 5 of `seed`), zero biases, output map y = raw scale +
+ * shift (initially identity).  Parameters are one flat array: W1 [n_in][h],
+ * b1, W2 [h][h], b2, W3 [h][n_out], b3. */
+int chebfd_mlp_create(chebfd_ctx *ctx, int n_in, int n_hidden, int n_out, uint64_t seed,
+                      chebfd_mlp **out);
+int chebfd_mlp_destroy(chebfd_mlp *mlp);
+int chebfd_mlp_num_params(const chebfd_mlp *mlp, int64_t *n);
+/* Copies parameters / output shift and scale (n_out each) to or from the host;
+ * any pointer may be NULL.  Synchronises. */
+int chebfd_mlp_get_params(chebfd_ctx *ctx, const chebfd_mlp *mlp, float *params, float *shift,
+                          float *scale);
+int chebfd_mlp_set_params(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *params,
+                          const float *shift, const float *scale);
+/* Input standardisation x -> (x - shift)/scale applied before the first
+ * layer (n_in floats each, host; identity at creation).  get = 1 copies the
+ * current values out instead.  Synchronises. */
+int chebfd_mlp_input_scaling(chebfd_ctx *ctx, chebfd_mlp *mlp, float *shift, float *scale,
+                             int get);
+/* Y = network(X) for `batch` rows (X: batch x n_in, Y: batch x n_out, device,
+ * row-major). */
+int chebfd_mlp_forward(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *X_dev, int batch,
+                       float *Y_dev);
+/* Mean-squared error between the raw outputs and the standardised targets
+ * (T - shift)/scale, and its gradient w.r.t. every parameter (host, may be
+ * NULL).  Synchronises. */
+int chebfd_mlp_loss_grad(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *X_dev,
+                         const float *T_dev, int batch, float *loss, float *grad);
+/* One Adam step (beta 0.9/0.999, eps 1e-8, decoupled weight decay) on the
+ * loss above; `loss` (host, may be NULL) receives the pre-step loss. */
+int chebfd_mlp_train_step(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *X_dev,
+                          const float *T_dev, int batch, float lr, float weight_decay,
+                          float *loss);
+
+/* ------------------------------------------------------------------ */
 /* the ChebFD solver (Sec. 3.1 steps 1-8)                              */
 /* ------------------------------------------------------------------ */
 

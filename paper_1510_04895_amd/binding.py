@@ -85,6 +85,21 @@ def lib():
         "chebfd_host_eigh": (i32, [i32, vp, vp]),
         "chebfd_set_tuning": (i32, [vp, C.c_char_p, i32]),
         "chebfd_bandwidth_probe": (i32, [vp, vp, i64, i32, vp]),
+        "chebfd_dos_params": (i32, [vp, i32, i64, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, vp,
+                                    vp, vp, vp]),
+        "chebfd_learned_features": (i32, [vp, i32, dbl, dbl, dbl, dbl, vp]),
+        "chebfd_learned_decode": (i32, [vp, i32, i32, i32, dbl, i32, vp, vp, vp, i32]),
+        "chebfd_fit_corrections": (i32, [dbl, dbl, dbl, dbl, dbl, dbl, i32, i32, dbl, i32, dbl,
+                                         i32, dbl, vp, vp]),
+        "chebfd_mlp_create": (i32, [vp, i32, i32, i32, u64, pp]),
+        "chebfd_mlp_destroy": (i32, [vp]),
+        "chebfd_mlp_num_params": (i32, [vp, vp]),
+        "chebfd_mlp_get_params": (i32, [vp, vp, vp, vp, vp]),
+        "chebfd_mlp_set_params": (i32, [vp, vp, vp, vp, vp]),
+        "chebfd_mlp_forward": (i32, [vp, vp, vp, i32, vp]),
+        "chebfd_mlp_input_scaling": (i32, [vp, vp, vp, vp, i32]),
+        "chebfd_mlp_loss_grad": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "chebfd_mlp_train_step": (i32, [vp, vp, vp, vp, i32, C.c_float, C.c_float, vp]),
         "chebfd_params_default": (i32, [vp]),
         "chebfd_solve_workspace_size": (i32, [vp, vp, vp]),
         "chebfd_solve": (i32, [vp, vp, vp, vp, i64, pp]),
@@ -109,7 +124,11 @@ def exported_symbols():
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
                         "chebfd_params_default chebfd_solve_workspace_size chebfd_solve "
                         "chebfd_result_get chebfd_result_destroy chebfd_set_tuning "
-                        "chebfd_bandwidth_probe").split()]
+                        "chebfd_bandwidth_probe chebfd_dos_params chebfd_learned_features "
+                        "chebfd_learned_decode chebfd_fit_corrections chebfd_mlp_create "
+                        "chebfd_mlp_destroy chebfd_mlp_num_params chebfd_mlp_get_params "
+                        "chebfd_mlp_set_params chebfd_mlp_forward chebfd_mlp_loss_grad "
+                        "chebfd_mlp_train_step chebfd_mlp_input_scaling").split()]
 
 
 def _check(rc, allow_warn=False):
@@ -314,6 +333,116 @@ def chebfd_kpm_moments(ctx, H, n_vec, n_mom, seed, a, b, precision=PREC_C64):
     out = np.empty(n_mom)
     _check(lib().chebfd_kpm_moments(ctx.h, H.h, precision, n_vec, n_mom, seed, a, b, _ptr(out)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# parameter choice and the learned form
+# ---------------------------------------------------------------------------
+def chebfd_dos_params(mu, n, a, b, lam_lo, lam_hi, ns_over_nt=3.0, kernel="lanczos", mu_k=2.0,
+                      ns_max=1024, n_s=0, with_margin=False):
+    m = _dbl(mu)
+    nt, ns, npp, mg = C.c_double(), C.c_int(n_s), C.c_int(), C.c_double()
+    k = KERNELS[kernel] if isinstance(kernel, str) else kernel
+    _check(lib().chebfd_dos_params(_ptr(m), m.size, n, a, b, lam_lo, lam_hi, ns_over_nt, k, mu_k,
+                                   ns_max, C.byref(nt), C.byref(ns), C.byref(npp), C.byref(mg)))
+    if with_margin:
+        return nt.value, ns.value, npp.value, mg.value
+    return nt.value, ns.value, npp.value
+
+
+def chebfd_learned_features(mu, a, b, lam_lo, lam_hi):
+    m = _dbl(mu)
+    f = np.empty(m.size + 2, np.float32)
+    _check(lib().chebfd_learned_features(_ptr(m), m.size, a, b, lam_lo, lam_hi, _ptr(f)))
+    return f
+
+
+def chebfd_learned_decode(out, np_ref, ns_ref, n_hat=64, c_max=0.5, ns_max=1024, corr_len=None):
+    o = np.ascontiguousarray(out, np.float32)
+    npp, ns = C.c_int(), C.c_int()
+    _check(lib().chebfd_learned_decode(_ptr(o), np_ref, ns_ref, n_hat, c_max, ns_max, C.byref(npp),
+                                       C.byref(ns), None, 0))
+    L = npp.value + 1 if corr_len is None else corr_len
+    corr = np.empty(L)
+    _check(lib().chebfd_learned_decode(_ptr(o), np_ref, ns_ref, n_hat, c_max, ns_max, C.byref(npp),
+                                       C.byref(ns), _ptr(corr), L))
+    return npp.value, ns.value, corr
+
+
+def chebfd_fit_corrections(a, b, t_lo, t_hi, s_lo, s_hi, n_p, kernel="lanczos", mu_k=2.0,
+                           n_hat=64, c_max=0.5, iters=150, l2=0.0):
+    amp = np.zeros(n_hat)
+    sig = C.c_double()
+    k = KERNELS[kernel] if isinstance(kernel, str) else kernel
+    _check(lib().chebfd_fit_corrections(a, b, t_lo, t_hi, s_lo, s_hi, n_p, k, mu_k, n_hat, c_max,
+                                        iters, l2, _ptr(amp), C.byref(sig)))
+    return amp, sig.value
+
+
+class MLP:
+    """Device network of the learned form (FP32)."""
+
+    def __init__(self, ctx, n_in, n_hidden, n_out, seed=1):
+        self.ctx, self.n_in, self.h, self.n_out = ctx, n_in, n_hidden, n_out
+        self.h_ = C.c_void_p()
+        _check(lib().chebfd_mlp_create(ctx.h, n_in, n_hidden, n_out, seed, C.byref(self.h_)))
+        n = C.c_int64()
+        _check(lib().chebfd_mlp_num_params(self.h_, C.byref(n)))
+        self.n_params = n.value
+
+    def get(self):
+        p = np.empty(self.n_params, np.float32)
+        sh = np.empty(self.n_out, np.float32)
+        sc = np.empty(self.n_out, np.float32)
+        _check(lib().chebfd_mlp_get_params(self.ctx.h, self.h_, _ptr(p), _ptr(sh), _ptr(sc)))
+        return p, sh, sc
+
+    def set(self, params=None, shift=None, scale=None):
+        f = (lambda a: None if a is None else np.ascontiguousarray(a, np.float32))
+        params, shift, scale = f(params), f(shift), f(scale)
+        _check(lib().chebfd_mlp_set_params(self.ctx.h, self.h_, _ptr(params), _ptr(shift),
+                                           _ptr(scale)))
+
+    def input_scaling(self, shift=None, scale=None):
+        """Sets (or, without arguments, returns) the input standardisation."""
+        if shift is None:
+            sh = np.empty(self.n_in, np.float32)
+            sc = np.empty(self.n_in, np.float32)
+            _check(lib().chebfd_mlp_input_scaling(self.ctx.h, self.h_, _ptr(sh), _ptr(sc), 1))
+            return sh, sc
+        sh = np.ascontiguousarray(shift, np.float32)
+        sc = np.ascontiguousarray(scale, np.float32)
+        _check(lib().chebfd_mlp_input_scaling(self.ctx.h, self.h_, _ptr(sh), _ptr(sc), 0))
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        _check(lib().chebfd_mlp_forward(self.ctx.h, self.h_, _ptr(X), X.shape[0], _ptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T):
+        loss = C.c_float()
+        g = np.empty(self.n_params, np.float32)
+        _check(lib().chebfd_mlp_loss_grad(self.ctx.h, self.h_, _ptr(X), _ptr(T), X.shape[0],
+                                          C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, X, T, lr, weight_decay=0.0):
+        loss = C.c_float()
+        _check(lib().chebfd_mlp_train_step(self.ctx.h, self.h_, _ptr(X), _ptr(T), X.shape[0],
+                                           lr, weight_decay, C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if self.h_:
+            lib().chebfd_mlp_destroy(self.h_)
+            self.h_ = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def default_params(**kw):

@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchebfd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.cpp", "matrix.cpp", "host_poly.cpp", "host_eig.cpp", "solver.cpp",
-           "kernels_step.hip", "kernels_stencil.hip", "kernels_dense.hip"]
+SOURCES = ["capi.cpp", "matrix.cpp", "host_poly.cpp", "host_eig.cpp", "solver.cpp", "learned.cpp",
+           "kernels_step.hip", "kernels_stencil.hip", "kernels_dense.hip", "kernels_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

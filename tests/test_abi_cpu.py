@@ -111,3 +111,49 @@ def test_host_eigh_degenerate_and_diagonal(B, orc):
     assert np.allclose(w, [-1.0, 0.5, 2.0, 2.0, 3.0])
     with pytest.raises(B.ChebFDError):
         B.chebfd_host_eigh(np.full((3, 3), np.nan, complex))
+
+
+def test_dos_params_count_and_rules(B, orc):
+    """N_T from KPM moments (Eq. DOS:target) against the exact count of a
+    small lattice; moments computed by the reference on random-phase
+    vectors (stochastic trace), so the count is approximate."""
+    H = orc.ti_hamiltonian(6, 6, 6, pbc=3, V=1.0, seed=2)
+    a, b = orc.gershgorin(H)
+    X = inp.random_phase_block(H.n, 24, seed=1)
+    mu = orc.moments_direct(H, a, b, X, 256).mean(1) / H.n
+    w = np.linalg.eigvalsh(H.dense())
+    for d in (0.8, 1.5):
+        exact = int((np.abs(w) <= d).sum())
+        nt, ns, n_p = B.chebfd_dos_params(mu, H.n, a, b, -d, d, ns_over_nt=3.0)
+        assert abs(nt - exact) <= 0.25 * exact + 4
+        assert ns >= 16 and ns % 2 == 0 and ns >= 3 * nt - 2
+        assert n_p > 8
+
+
+def test_fit_corrections_lowers_sigma(B, orc):
+    """The fitted hat amplitudes lower the damping factor sigma of Sec. 2.3,
+    as evaluated independently by the reference on the corrected
+    coefficients decoded by the library."""
+    a, b, d = -1.0, 1.0, 0.02
+    t_lo, t_hi, s_lo, s_hi = -d, d, -2 * d, 2 * d
+    n_p = 300
+    amp, sig_fit = B.chebfd_fit_corrections(a, b, t_lo, t_hi, s_lo, s_hi, n_p, iters=150)
+    g0 = orc.gamma(t_lo, t_hi, a, b, n_p)
+    s_plain, _ = orc.filter_quality(g0, a, b, t_lo, t_hi, s_lo, s_hi)
+    out = np.concatenate([[0.0, 0.0], amp]).astype(np.float32)
+    n_p2, ns, corr = B.chebfd_learned_decode(out, n_p, 64)
+    assert n_p2 == n_p and ns == 64 and corr.size == n_p + 1
+    s_corr, _ = orc.filter_quality(g0 * (1 + corr), a, b, t_lo, t_hi, s_lo, s_hi)
+    assert s_corr < 0.9 * s_plain
+    # a zero network output leaves the expansion unchanged
+    n0, s0, c0 = B.chebfd_learned_decode(np.zeros(66, np.float32), 500, 40)
+    assert n0 == 500 and s0 == 40 and np.all(c0 == 0.0)
+    n1, s1, _ = B.chebfd_learned_decode(np.r_[np.log(2.0), -np.log(2.0), np.zeros(64)], 500, 40)
+    assert n1 == 1000 and s1 == 20
+
+
+def test_learned_features_layout(B):
+    mu = np.linspace(1, 0, 10)
+    f = B.chebfd_learned_features(mu, -4.0, 4.0, -0.4, 0.2)
+    assert f.dtype == np.float32 and f.size == 12
+    assert np.allclose(f[:10], mu) and np.allclose(f[10:], [-0.1, 0.05])

@@ -257,3 +257,42 @@ def test_solve_small_lattice_vs_dense(env, orc, storage, prec, lock):
     r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
     assert r.max() <= 1.05e-9
     assert np.abs(V.conj().T @ V - np.eye(4)).max() < 1e-9
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+def test_solve_ti_8x8x8_vs_golden(env, orc, seed, storage):
+    """The correctness configuration: 8x8x8 lattice, window holding the 16
+    eigenvalues of smallest modulus (dense spectrum from the oracle's
+    Jacobi, stored under tests/golden), N_S = 32, N_p = 200, Lanczos kernel."""
+    import os
+    torch, B, ctx = env
+    w = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                f"ti_8x8x8_V1_seed{seed}_evals.txt"))
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[15] + aw[16])
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=seed, storage=st)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=200, eps=1e-9, seed=seed + 1000,
+                         max_iter=200)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    want = w[np.abs(w) <= d]
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0, stats
+    assert want.size == 16 and ev.size == 16
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    Hr = orc.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=seed)
+    r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
+    assert r.max() <= 1.05e-9
+    assert np.abs(V.conj().T @ V - np.eye(16)).max() < 1e-8
+
+
+def test_solve_is_bitwise_reproducible(env):
+    """Fixed-order reductions everywhere: two runs give identical bits."""
+    torch, B, ctx = env
+    H = B.Matrix.ti(ctx, (6, 6, 4), pbc=3, V=1.0, seed=9)
+    p = B.default_params(lam_lo=-0.6, lam_hi=0.6, n_s=24, n_p=80, eps=1e-9, seed=5)
+    r1 = B.chebfd_solve(ctx, H, p)
+    r2 = B.chebfd_solve(ctx, H, p)
+    assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
+    assert np.array_equal(r1[3], r2[3])

@@ -199,3 +199,17 @@ def test_table_num_linear_iterations_scaled(orc):
     assert want.size == 10 and ev.size == 10
     assert np.abs(ev - want).max() < 1e-12
     assert 4 <= stats["iterations"] - 1 <= 6
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_golden_dense_spectra_vs_lapack(orc, seed):
+    """The stored 8x8x8 spectra (written by the oracle's Jacobi) agree with
+    LAPACK on the oracle's matrix, and come in exact Kramers pairs."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"ti_8x8x8_V1_seed{seed}_evals.txt")
+    w = np.loadtxt(path)
+    H = orc.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=seed)
+    wl = np.linalg.eigvalsh(H.dense())
+    assert w.size == 2048
+    assert np.abs(w - wl).max() < 1e-11
+    assert np.abs(w[0::2] - w[1::2]).max() < 1e-11
