@@ -33,8 +33,8 @@ import numpy as np  # noqa: E402
 import chebfd_inputs as inp  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h"],
-                  "stencil": ["kernels_stencil.hip", "pack.h"]}
+KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h", "dispatch.h"],
+                  "stencil": ["kernels_stencil.hip", "pack.h", "dispatch.h"]}
 
 
 def source_sha(storage):

@@ -227,9 +227,20 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *                 0 = default (32; 16 for blocks of at most 16 packs);
  *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
  *   "order"       0 (default) = workgroups ordered column-slab major,
- *                 1 = row-chunk major;
- *   "gathers"     SELL only: gathered rows in flight per row, 8 (default) or 16.
- * Results are identical for every setting; only speed changes.
+ *                 1 = row-chunk major, 2 = lattice z-march (matrices from
+ *                 chebfd_matrix_ti: blocks of one z-column run consecutively
+ *                 on one XCD; other matrices fall back to 0);
+ *   "gathers"     SELL only: gathered rows in flight per row, 8 or 16 (default);
+ *   "pipeline"    SELL only: 0 (default) = one row block per workgroup,
+ *                 1 = persistent workgroups that stage the next row block
+ *                 while the current one is gathered;
+ *   "xcd_group"   consecutive workgroups placed on one of the 8 XCDs (each
+ *                 with its own L2): 1 = hardware round-robin order, a power
+ *                 of two up to 64, 0 = default (SELL: the workgroups of one
+ *                 chunk; stencil: 1).
+ * The filtered blocks are bitwise identical for every setting (each element
+ * is computed by the same operations in the same order); moment sums may
+ * differ in rounding; only speed changes.
  * Errors: INVALID_ARG for an unknown key or value. */
 int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value);
 

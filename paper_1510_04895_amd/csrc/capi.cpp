@@ -97,9 +97,8 @@ int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double
     double *part = nullptr;
     int64_t n_part = 0;
     if (mom) {
-        // partial sums: one row of 3 per column per chunk/site block
-        const int64_t rows_blk = H->storage == CHEBFD_STORAGE_SELL ? H->sell.C : 16;
-        const int64_t nparts = (H->n + rows_blk - 1) / rows_blk + 1;
+        // partial sums: one row of 3 per column per workgroup row block
+        const int64_t nparts = step_partial_blocks(ctx, H, prec, n_s);
         int rc = ensure_scratch(ctx, (size_t)nparts * n_s * 3 * sizeof(double));
         if (rc) return rc;
         part = (double *)ctx->scratch;
@@ -343,8 +342,11 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     const std::string k(key);
     if (k == "lanes" && (value == 0 || value == 16 || value == 32 || value == 64)) ctx->tune_lpr = value;
     else if (k == "nontemporal" && (value == 0 || value == 1)) ctx->tune_nt = value;
-    else if (k == "order" && (value == 0 || value == 1)) ctx->tune_order = value;
+    else if (k == "order" && value >= 0 && value <= 2) ctx->tune_order = value;
     else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
+    else if (k == "pipeline" && (value == 0 || value == 1)) ctx->tune_pipeline = value;
+    else if (k == "xcd_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
+        ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");
     return CHEBFD_OK;
 }

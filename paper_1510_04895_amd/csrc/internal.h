@@ -47,6 +47,11 @@ struct Sell {
     int32_t *col = nullptr;         // stored
     double *val64 = nullptr;        // stored complex128 (interleaved)
     float *val32 = nullptr;         // stored complex64
+    // optional traversal order of the chunks (a permutation; nullptr =
+    // natural order) and the number of consecutive scheduled chunks that
+    // form one locality group (a z-column of a lattice)
+    int32_t *sched = nullptr;
+    int sched_group = 0;
 };
 
 struct Stencil {
@@ -72,7 +77,9 @@ struct chebfd_ctx {
     int tune_lpr = 0;     // lanes per row/site: 0 = default (32), 16, 32, 64
     int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
     int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
-    int tune_gathers = 8; // gathers in flight per row (SELL): 8 or 16
+    int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
+    int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
+    int tune_xcd_group = 0; // consecutive workgroups per XCD: 0 = default, 1 = hardware order
 };
 
 struct chebfd_matrix {
@@ -110,6 +117,9 @@ struct StepArgs {
 // Launches one fused step; returns number of partial-sum rows written
 // (per column triples) in *n_part when partials != nullptr.
 int launch_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a, int64_t *n_part);
+// Number of per-workgroup moment partial rows one step launch writes.
+int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                            int64_t n_s);
 
 // Sums the moment partials of one step into the moment array.
 int launch_moment_finalize(chebfd_ctx *ctx, const double *partials, int64_t n_part,

@@ -14,6 +14,7 @@
 // j = x, y (s_x = 1, s_y = -i/+i) or kept for j = z (s_z = +1/-1).
 #include <type_traits>
 
+#include "dispatch.h"
 #include "internal.h"
 #include "pack.h"
 
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                                                  const T *wold, T *wout, T *y, int64_t n_s,
                                                  int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
                                                  double *__restrict__ partials, int order,
-                                                 int64_t nslab)
+                                                 int64_t nslab, int lg_xg)
 {
     constexpr int SPW = 64 / LPS;   // sites per wave
     constexpr int SPB = 4 * SPW;    // sites per workgroup
@@ -83,19 +84,39 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int ssub = lane / LPS, cl = lane % LPS;
-    const int64_t b = blockIdx.x;
-    int64_t slab, sb;
-    if (order == 0) {
-        slab = b / nblk;
-        sb = b - slab * nblk;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x, lg_xg);
+    int64_t slab, sb, site;
+    bool in_lattice;
+    if (order == 2) {
+        // z-march: a block is SPB x-consecutive sites of one (y, z); the
+        // logical order runs z fastest, then x-blocks, then y, then slabs, so
+        // the z-neighbour planes of a block were gathered by the block just
+        // before it (on the same XCD when 2^lg_xg consecutive blocks share one)
+        const int64_t nxb = (Lx + SPB - 1) / SPB;
+        const int64_t nper = nxb * Ly * Lz;
+        slab = b / nper;
+        sb = b - slab * nper;
+        const int64_t t = sb / Lz;
+        const int z = (int)(sb - t * Lz);
+        const int64_t yb = t / nxb;
+        const int xb = (int)(t - yb * nxb);
+        const int x = xb * SPB + wave * SPW + ssub;
+        in_lattice = x < Lx;
+        site = x + (int64_t)Lx * (yb + (int64_t)Ly * z);
     } else {
-        sb = b / nslab;
-        slab = b - sb * nslab;
+        if (order == 0) {
+            slab = b / nblk;
+            sb = b - slab * nblk;
+        } else {
+            sb = b / nslab;
+            slab = b - sb * nslab;
+        }
+        site = sb * SPB + wave * SPW + ssub;
+        in_lattice = site < nsites;
     }
     const int64_t c0 = slab * SW + (int64_t)cl * NB;
     const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);
-    const int64_t site = sb * SPB + wave * SPW + ssub;
-    const bool active = c0 < n_s && site < nsites;
+    const bool active = c0 < n_s && in_lattice;
 
     double m0[NB], m1[NB], m2[NB];
 #pragma unroll
@@ -273,15 +294,23 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     constexpr int SPB = 4 * (64 / LPS);
     constexpr int SW = LPS * NB;
     const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
-    const int64_t nblk = (nsites + SPB - 1) / SPB;
+    const int order = ctx->tune_order;
+    // z-march blocks cover whole x-runs of SPB sites (the last one ragged)
+    const int64_t nblk = order == 2 ? (S.L[0] + SPB - 1) / SPB * S.L[1] * S.L[2]
+                                    : (nsites + SPB - 1) / SPB;
     const int64_t nslab = (a.n_s + SW - 1) / SW;
+    if (nblk * nslab >= ((int64_t)1 << 31))
+        return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
     if (n_part) *n_part = nblk;
+    // default placement for the z-march: one z-column of blocks per XCD group
+    int lg_xg = ilog2(ctx->tune_xcd_group);
+    if (order == 2 && !ctx->tune_xcd_group) lg_xg = ilog2(S.L[2]);
     const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
     hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
                        dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,
                        (T)(-0.5 * S.t), (T)S.m, pot, nsites, nblk, (const T *)a.u,
                        (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld, (T)a.s_h,
-                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, ctx->tune_order, nslab);
+                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, order, nslab, lg_xg);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }

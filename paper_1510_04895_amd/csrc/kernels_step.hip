@@ -18,17 +18,105 @@
 // slab wide.
 #include <type_traits>
 
+#include "dispatch.h"
 #include "internal.h"
 #include "pack.h"
 
 namespace chebfd {
 namespace {
 
-// Accumulates one row of the sparse product from (index, value) pairs
-// served by `src(j)`, GB gathers in flight at a time.
-template <typename T, int NB, int GB, typename Src>
-__device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld, int64_t c0,
-                                            int cnt, int len, Src src, T (&ar)[NB], T (&ai)[NB])
+// Complex matrix value j of a SELL stream as (re, im), one vector load, and
+// its LDS counterpart.
+template <typename T>
+struct CVal;
+template <>
+struct CVal<double> {
+    typedef d2v V;
+};
+template <>
+struct CVal<float> {
+    typedef float V __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__device__ __forceinline__ void load_value(const T *val, int64_t j, T &re, T &im)
+{
+    const typename CVal<T>::V v = *reinterpret_cast<const typename CVal<T>::V *>(val + 2 * j);
+    re = v.x;
+    im = v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_value(T *p, T re, T im)
+{
+    typename CVal<T>::V v;
+    v.x = re;
+    v.y = im;
+    *reinterpret_cast<typename CVal<T>::V *>(p) = v;
+}
+
+// Block row r of a row-major block as a byte offset from the lane's column
+// base: one 32x32->64-bit multiply-add per gather (row_bytes = ld * entry
+// size, checked on the host to fit 32 bits).
+template <typename T>
+__device__ __forceinline__ const T *row_at(const char *ub, uint32_t r, uint32_t row_bytes)
+{
+    return reinterpret_cast<const T *>(ub + (uint64_t)r * row_bytes);
+}
+
+constexpr int LS = 32;   // staged entries per row; longer rows read the stream directly
+
+// Accumulates one row of the sparse product from the LDS stage.  The stage
+// keeps the SELL order (entry j of block row q at j*RPP + q) and pads every
+// row past its length up to LS entries with the row itself and value 0, so
+// all GB column indices and values of a batch can be read unguarded; all
+// gathers of the batch are issued before the first value is used.
+template <typename T, int NB, int GB, int RPP>
+__device__ __forceinline__ void row_product_staged(const char *ub, uint32_t row_bytes, int cnt,
+                                                   int len, const int32_t *scol, const T *sval,
+                                                   T (&ar)[NB], T (&ai)[NB])
+{
+    static_assert(LS % GB == 0, "batches tile the LDS line");
+#pragma unroll
+    for (int e = 0; e < NB; ++e) ar[e] = ai[e] = T(0);
+    for (int j = 0; j < len; j += GB) {
+        int ci[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) ci[i] = scol[(j + i) * RPP];
+        // the length is uniform over the workgroup: the guards are scalar
+        // branches, and padded entries (row itself, value 0) past len are
+        // neither gathered nor used
+        Pack<T, NB> g[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+            if (j + i < len) {
+                g[i] = load_pack_n<T, NB>(row_at<T>(ub, ci[i], row_bytes), cnt);
+            } else {
+#pragma unroll
+                for (int e = 0; e < NB; ++e) g[i].re[e] = g[i].im[e] = T(0);
+            }
+        }
+        // keep the whole batch in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+            T hr, hi;
+            load_value<T>(sval, (int64_t)(j + i) * RPP, hr, hi);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                ar[e] += hr * g[i].re[e] - hi * g[i].im[e];
+                ai[e] += hr * g[i].im[e] + hi * g[i].re[e];
+            }
+        }
+    }
+}
+
+// The same from the global index stream (rows longer than the LDS stage).
+template <typename T, int NB, int GB>
+__device__ __forceinline__ void row_product_stream(const char *ub, uint32_t row_bytes, int cnt,
+                                                   int len, const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val, int64_t e0,
+                                                   int C, T (&ar)[NB], T (&ai)[NB])
 {
 #pragma unroll
     for (int e = 0; e < NB; ++e) ar[e] = ai[e] = T(0);
@@ -38,9 +126,9 @@ __device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld,
 #pragma unroll
         for (int i = 0; i < GB; ++i) {
             if (j + i < len) {
-                int ci;
-                src(j + i, ci, hr[i], hi[i]);
-                g[i] = load_pack_n<T, NB>(u + 2 * ((int64_t)ci * ld + c0), cnt);
+                const int64_t e = e0 + (int64_t)(j + i) * C;
+                load_value<T>(val, e, hr[i], hi[i]);
+                g[i] = load_pack_n<T, NB>(row_at<T>(ub, (uint32_t)col[e], row_bytes), cnt);
             }
         }
 #pragma unroll
@@ -56,174 +144,327 @@ __device__ __forceinline__ void row_product(const T *__restrict__ u, int64_t ld,
     }
 }
 
-constexpr int LDS_ENTRIES = 1024;   // index/value pairs of one chunk staged in LDS
+// Workgroup barrier that orders LDS only: the wave's outstanding global
+// loads and stores stay in flight across it (a plain __syncthreads would
+// wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
+// A unit of work: RB <= C consecutive rows of one chunk (a row block) times
+// one column slab.  32-bit indices (the host checks the counts).
+struct BlockLoc {
+    uint32_t slab, rb, chunk, r0, len;
+    int64_t base;
+};
+
+// Logical work item l -> block.  order 0: slab-major (all row blocks of a
+// column slab, then the next slab); order 1: block-major.  The row blocks
+// per chunk are a power of two (2^lg_bpc).  With a schedule, the row blocks
+// visit the chunks in the scheduled order.
+__device__ __forceinline__ BlockLoc locate(uint32_t l, int order, uint32_t nrb, uint32_t nslab,
+                                          int C, int lg_bpc, int RB,
+                                          const int64_t *__restrict__ chunk_ptr,
+                                          const int32_t *__restrict__ chunk_len,
+                                          const int32_t *__restrict__ sched)
+{
+    BlockLoc L;
+    if (order == 0) {
+        L.slab = l / nrb;
+        L.rb = l - L.slab * nrb;
+    } else {
+        L.rb = l / nslab;
+        L.slab = l - L.rb * nslab;
+    }
+    L.chunk = sched ? (uint32_t)sched[L.rb >> lg_bpc] : L.rb >> lg_bpc;
+    L.r0 = (L.rb & ((1u << lg_bpc) - 1)) * RB;
+    L.len = chunk_len[L.chunk];
+    L.base = chunk_ptr[L.chunk];
+    return L;
+}
+
+// The block's index/value stream in LDS, in SELL order: lane t carries
+// entry t = j*RPP + q, so both the global loads (consecutive rows of one
+// SELL column) and the LDS stores are contiguous.  Entries past a row's
+// length become (row itself, 0).
+template <typename T, int RPP>
+struct Stage {
+    static constexpr int PER = (RPP * LS + 255) / 256;
+    int32_t cc[PER];
+    T vr[PER], vi[PER];
+    int32_t prow;   // perm entry of block row tid % RPP (-1: no row)
+};
+
+template <typename T, int RPP>
+__device__ __forceinline__ void stage_load(Stage<T, RPP> &st, const BlockLoc &L, int tid, int C,
+                                           int RB, const int32_t *__restrict__ perm,
+                                           const int32_t *__restrict__ col,
+                                           const T *__restrict__ val)
+{
+    static_assert(256 % RPP == 0, "a lane stages one block row");
+    const int qq = tid % RPP;
+    st.prow = qq < RB ? perm[(int64_t)L.chunk * C + L.r0 + qq] : -1;
+#pragma unroll
+    for (int k = 0; k < Stage<T, RPP>::PER; ++k) {
+        const int t = tid + 256 * k, jj = t / RPP;
+        if (t < RPP * LS && qq < RB && jj < (int)L.len) {
+            const int64_t e = L.base + (int64_t)jj * C + L.r0 + qq;
+            st.cc[k] = col[e];
+            load_value<T>(val, e, st.vr[k], st.vi[k]);
+        }
+    }
+}
+
+template <typename T, int RPP>
+__device__ __forceinline__ void stage_store(const Stage<T, RPP> &st, const BlockLoc &L, int tid,
+                                            int RB, int32_t *s_col, T *s_val, int32_t *s_row)
+{
+    const int qq = tid % RPP;
+#pragma unroll
+    for (int k = 0; k < Stage<T, RPP>::PER; ++k) {
+        const int t = tid + 256 * k, jj = t / RPP;
+        if (t < RPP * LS && qq < RB) {
+            const bool in = jj < (int)L.len;
+            s_col[t] = in ? st.cc[k] : st.prow;
+            store_value<T>(s_val + 2 * t, in ? st.vr[k] : T(0), in ? st.vi[k] : T(0));
+        }
+    }
+    if (tid < RPP) s_row[tid] = st.prow;
+}
+
+// The fused step on one row and one pack of columns (modes as above), with
+// the moment dot products accumulated in m0..m2.
+template <typename T, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, int RPP>
+__device__ __forceinline__ void step_row(int row, int64_t c0, int cnt, int len,
+                                         const int32_t *scol, const T *sval,
+                                         const int32_t *__restrict__ col,
+                                         const T *__restrict__ val, int64_t e0, int C,
+                                         const T *__restrict__ u, const T *wold, T *wout, T *y,
+                                         int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
+                                         double (&m0)[NB], double (&m1)[NB], double (&m2)[NB])
+{
+    const uint32_t row_bytes = (uint32_t)(ld * 2 * sizeof(T));
+    const char *ub = reinterpret_cast<const char *>(u + 2 * c0);
+    // the row's own operands first: they do not depend on the product
+    const int64_t off = 2 * ((int64_t)row * ld + c0);
+    const Pack<T, NB> uo = load_pack_n<T, NB>(u + off, cnt);
+    Pack<T, NB> wo, yv;
+    if (MODE == MODE_SECOND || MODE == MODE_STEP) wo = load_pack_n<T, NB, NT>(wold + off, cnt);
+    if (MODE == MODE_STEP) yv = load_pack_n<T, NB, NT>(y + off, cnt);
+    T ar[NB], ai[NB];
+    if (STAGED)
+        row_product_staged<T, NB, GB, RPP>(ub, row_bytes, cnt, len, scol, sval, ar, ai);
+    else
+        row_product_stream<T, NB, GB>(ub, row_bytes, cnt, len, col, val, e0, C, ar, ai);
+    Pack<T, NB> w;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        w.re[e] = s_h * ar[e] + s_u * uo.re[e];
+        w.im[e] = s_h * ai[e] + s_u * uo.im[e];
+    }
+    if (MODE == MODE_APPLY) {
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        if (MOM) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                const double xr = uo.re[e], xi = uo.im[e], wr = w.re[e], wi = w.im[e];
+                m0[e] += xr * xr + xi * xi;
+                m1[e] += xr * wr + xi * wi;
+                m2[e] += wr * wr + wi * wi;
+            }
+        }
+    } else if (MODE == MODE_SECOND) {
+        const Pack<T, NB> xo = wo;
+        Pack<T, NB> xn;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            w.re[e] -= xo.re[e];
+            w.im[e] -= xo.im[e];
+            xn.re[e] = g0 * xo.re[e] + g1 * uo.re[e] + g2 * w.re[e];
+            xn.im[e] = g0 * xo.im[e] + g1 * uo.im[e] + g2 * w.im[e];
+        }
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        store_pack_n<T, NB, NT>(y + off, xn, cnt);
+        if (MOM) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
+                m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            w.re[e] -= wo.re[e];
+            w.im[e] -= wo.im[e];
+            yv.re[e] += g0 * w.re[e];
+            yv.im[e] += g0 * w.im[e];
+        }
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        store_pack_n<T, NB, NT>(y + off, yv, cnt);
+        if (MOM) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
+                m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
+            }
+        }
+    }
+}
+
+// Per-column moment partials of one row block: reduce over the rows of the
+// wave (lanes with the same column), then over the four waves through LDS,
+// in a fixed order; row block rb writes its own partial row.
+template <int LPR, int NB>
+__device__ __forceinline__ void moment_partials(double (&m0)[NB], double (&m1)[NB],
+                                                double (&m2)[NB], double (*red)[64][3 * NB],
+                                                int wave, int lane, int64_t rb, int64_t c0,
+                                                int cnt, int64_t n_s, double *partials)
+{
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        for (int off = LPR; off < 64; off <<= 1) {
+            m0[e] += __shfl_xor(m0[e], off);
+            m1[e] += __shfl_xor(m1[e], off);
+            m2[e] += __shfl_xor(m2[e], off);
+        }
+        red[wave][lane][3 * e + 0] = m0[e];
+        red[wave][lane][3 * e + 1] = m1[e];
+        red[wave][lane][3 * e + 2] = m2[e];
+    }
+    lds_barrier();
+    if (wave == 0 && lane < LPR && c0 < n_s) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            if (e >= cnt) continue;
+            double *p = partials + 3 * (rb * n_s + c0 + e);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                p[q] = red[0][lane][3 * e + q] + red[1][lane][3 * e + q] +
+                       red[2][lane][3 * e + q] + red[3][lane][3 * e + q];
+        }
+    }
+    lds_barrier();   // red is reused by the next block
+}
+
+// One row block per workgroup (used for rows longer than the LDS stage,
+// which read the index stream directly, and as a tuning alternative).
 template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
 __global__ __launch_bounds__(256) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
-    const T *__restrict__ val, int C, int64_t nchunks, const T *__restrict__ u,
-    const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
-    double *__restrict__ partials, int order, int64_t nslab)
+    const int32_t *__restrict__ sched, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ col,
+    const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
+    const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
+    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int order, uint32_t nslab,
+    int lg_xg)
 {
     constexpr int RPW = 64 / LPR;        // rows per wave
-    constexpr int RPP = 4 * RPW;         // rows per pass of the workgroup
+    constexpr int RPP = 4 * RPW;         // rows per workgroup
     constexpr int SW = LPR * NB;         // slab width in complex columns
-    __shared__ int32_t s_col[LDS_ENTRIES];
-    __shared__ T s_val[2 * LDS_ENTRIES];
+    __shared__ __align__(16) int32_t s_col[STAGED ? RPP * LS : 4];
+    __shared__ __align__(16) T s_val[STAGED ? 2 * RPP * LS : 2];
+    __shared__ int32_t s_row[RPP];
+    __shared__ double red[MOM ? 4 : 1][64][3 * NB];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int rsub = lane / LPR, cl = lane % LPR;
-    const int64_t b = blockIdx.x;
-    // order 0: slab-major (all chunks of a column slab, then the next slab);
-    // order 1: chunk-major (all slabs of a chunk adjacent)
-    int64_t slab, chunk;
-    if (order == 0) {
-        slab = b / nchunks;
-        chunk = b - slab * nchunks;
-    } else {
-        chunk = b / nslab;
-        slab = b - chunk * nslab;
-    }
-    const int64_t c0 = slab * SW + (int64_t)cl * NB;
-    const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);   // valid columns of the pack
-    const bool active = c0 < n_s;
-    const int len = chunk_len[chunk];
-    const int64_t base = chunk_ptr[chunk];
-    // chunks that fit are staged in LDS with coalesced loads, so the gathers
-    // of a row never wait on an index load; wider chunks read the stream
-    // directly
-    constexpr bool staged = STAGED;
-    if (staged) {
-        for (int t = tid; t < len * C; t += 256) {
-            s_col[t] = col[base + t];
-            s_val[2 * t] = val[2 * (base + t)];
-            s_val[2 * t + 1] = val[2 * (base + t) + 1];
+    const BlockLoc L = locate(xcd_remap(blockIdx.x, gridDim.x, lg_xg), order, nrb, nslab, C,
+                              lg_bpc, RB, chunk_ptr, chunk_len, sched);
+    {
+        Stage<T, RPP> st;
+        if (STAGED) {
+            stage_load<T, RPP>(st, L, tid, C, RB, perm, col, val);
+            stage_store<T, RPP>(st, L, tid, RB, s_col, s_val, s_row);
+        } else if (tid < RPP) {
+            s_row[tid] = tid < RB ? perm[(int64_t)L.chunk * C + L.r0 + tid] : -1;
         }
-        __syncthreads();
+        lds_barrier();
     }
-
+    const int q = wave * RPW + rsub;     // block row of this lane
+    const int64_t c0 = (int64_t)L.slab * SW + (int64_t)cl * NB;
+    const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);   // valid columns of the pack
+    const int row = s_row[q];
     double m0[NB], m1[NB], m2[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
+    if (c0 < n_s && row >= 0)
+        step_row<T, NB, MODE, MOM, NT, STAGED, GB, RPP>(
+            row, c0, cnt, L.len, s_col + q, s_val + 2 * q, col, val, L.base + L.r0 + q, C, u,
+            wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
+    if (MOM) moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
+}
 
-    for (int r = wave * RPW + rsub; r < C; r += RPP) {
-        const int row = perm[chunk * C + r];
-        if (row < 0 || !active) continue;
-        // the row's own operands first: they do not depend on the product
-        const int64_t off = 2 * ((int64_t)row * ld + c0);
-        const Pack<T, NB> uo = load_pack_n<T, NB>(u + off, cnt);
-        Pack<T, NB> wo, yv;
-        if (MODE == MODE_SECOND || MODE == MODE_STEP) wo = load_pack_n<T, NB, NT>(wold + off, cnt);
-        if (MODE == MODE_STEP) yv = load_pack_n<T, NB, NT>(y + off, cnt);
-        T ar[NB], ai[NB];
-        if (staged) {
-            row_product<T, NB, GB>(u, ld, c0, cnt, len,
-                                   [&](int j, int &ci, T &hr, T &hi) {
-                                       const int t = j * C + r;
-                                       ci = s_col[t];
-                                       hr = s_val[2 * t];
-                                       hi = s_val[2 * t + 1];
-                                   },
-                                   ar, ai);
-        } else {
-            const int64_t eb = base + r;
-            row_product<T, NB, GB>(u, ld, c0, cnt, len,
-                                   [&](int j, int &ci, T &hr, T &hi) {
-                                       const int64_t e = eb + (int64_t)j * C;
-                                       ci = col[e];
-                                       hr = val[2 * e];
-                                       hi = val[2 * e + 1];
-                                   },
-                                   ar, ai);
-        }
-        Pack<T, NB> w;
-#pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            w.re[e] = s_h * ar[e] + s_u * uo.re[e];
-            w.im[e] = s_h * ai[e] + s_u * uo.im[e];
-        }
-        if (MODE == MODE_APPLY) {
-            store_pack_n<T, NB, NT>(wout + off, w, cnt);
-            if (MOM) {
-#pragma unroll
-                for (int e = 0; e < NB; ++e) {
-                    const double xr = uo.re[e], xi = uo.im[e], wr = w.re[e], wi = w.im[e];
-                    m0[e] += xr * xr + xi * xi;
-                    m1[e] += xr * wr + xi * wi;
-                    m2[e] += wr * wr + wi * wi;
-                }
-            }
-        } else if (MODE == MODE_SECOND) {
-            const Pack<T, NB> xo = wo;
-            Pack<T, NB> xn;
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                w.re[e] -= xo.re[e];
-                w.im[e] -= xo.im[e];
-                xn.re[e] = g0 * xo.re[e] + g1 * uo.re[e] + g2 * w.re[e];
-                xn.im[e] = g0 * xo.im[e] + g1 * uo.im[e] + g2 * w.im[e];
-            }
-            store_pack_n<T, NB, NT>(wout + off, w, cnt);
-            store_pack_n<T, NB, NT>(y + off, xn, cnt);
-            if (MOM) {
-#pragma unroll
-                for (int e = 0; e < NB; ++e) {
-                    m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
-                    m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                w.re[e] -= wo.re[e];
-                w.im[e] -= wo.im[e];
-                yv.re[e] += g0 * w.re[e];
-                yv.im[e] += g0 * w.im[e];
-            }
-            store_pack_n<T, NB, NT>(wout + off, w, cnt);
-            store_pack_n<T, NB, NT>(y + off, yv, cnt);
-            if (MOM) {
-#pragma unroll
-                for (int e = 0; e < NB; ++e) {
-                    m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
-                    m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
-                }
-            }
-        }
+// Persistent, software-pipelined form of the staged kernel: each workgroup
+// walks the logical work items v = blockIdx.x, + gridDim.x, ... (gridDim.x a
+// multiple of the XCD count, so a workgroup stays on one XCD's sequence) and
+// stages the next block's index/value stream into the other LDS buffer while
+// the current block's gathers are in flight.  The block metadata is fetched
+// two blocks ahead.
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, int GB>
+__global__ __launch_bounds__(256) void k_step_sell_pipe(
+    const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
+    const int32_t *__restrict__ sched, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ col,
+    const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
+    const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
+    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int order, uint32_t nslab,
+    int lg_xg)
+{
+    constexpr int RPW = 64 / LPR;
+    constexpr int RPP = 4 * RPW;
+    constexpr int SW = LPR * NB;
+    __shared__ __align__(16) int32_t s_col[2][RPP * LS];
+    __shared__ __align__(16) T s_val[2][2 * RPP * LS];
+    __shared__ int32_t s_row[2][RPP];
+    __shared__ double red[MOM ? 4 : 1][64][3 * NB];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int rsub = lane / LPR, cl = lane % LPR;
+    const int q = wave * RPW + rsub;
+    const uint32_t total = nrb * nslab, G = gridDim.x;
+    auto at = [&](uint32_t v) {
+        return locate(xcd_remap(v, total, lg_xg), order, nrb, nslab, C, lg_bpc, RB, chunk_ptr,
+                      chunk_len, sched);
+    };
+    uint32_t v = blockIdx.x;
+    BlockLoc cur = at(v);
+    BlockLoc nxt = (v + G < total) ? at(v + G) : cur;
+    {
+        Stage<T, RPP> st;
+        stage_load<T, RPP>(st, cur, tid, C, RB, perm, col, val);
+        stage_store<T, RPP>(st, cur, tid, RB, s_col[0], s_val[0], s_row[0]);
     }
-
-    if (MOM) {
-        // reduce over the rows of the wave (lanes with the same column), then
-        // over the four waves through LDS, in a fixed order
-        __shared__ double red[4][64][3 * NB];
+    lds_barrier();
+    int buf = 0;
+    for (; v < total; v += G) {
+        const bool has_next = v + G < total;
+        // next block's stream: issued before this block's gathers
+        Stage<T, RPP> st;
+        if (has_next) stage_load<T, RPP>(st, nxt, tid, C, RB, perm, col, val);
+        const int64_t c0 = (int64_t)cur.slab * SW + (int64_t)cl * NB;
+        const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);
+        const int row = s_row[buf][q];
+        double m0[NB], m1[NB], m2[NB];
 #pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            for (int off = LPR; off < 64; off <<= 1) {
-                m0[e] += __shfl_xor(m0[e], off);
-                m1[e] += __shfl_xor(m1[e], off);
-                m2[e] += __shfl_xor(m2[e], off);
-            }
-            red[wave][lane][3 * e + 0] = m0[e];
-            red[wave][lane][3 * e + 1] = m1[e];
-            red[wave][lane][3 * e + 2] = m2[e];
-        }
-        __syncthreads();
-        if (wave == 0 && lane < LPR && active) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                if (e >= cnt) continue;
-                double sq[3];
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    sq[q] = red[0][lane][3 * e + q] + red[1][lane][3 * e + q] +
-                            red[2][lane][3 * e + q] + red[3][lane][3 * e + q];
-                double *p = partials + 3 * (chunk * n_s + c0 + e);
-                p[0] = sq[0];
-                p[1] = sq[1];
-                p[2] = sq[2];
-            }
-        }
+        for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
+        if (c0 < n_s && row >= 0)
+            step_row<T, NB, MODE, MOM, NT, true, GB, RPP>(
+                row, c0, cnt, cur.len, s_col[buf] + q, s_val[buf] + 2 * q, col, val, 0, C, u,
+                wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
+        // metadata two blocks ahead; its latency is hidden by a whole block
+        const BlockLoc nn = (v + 2 * G < total) ? at(v + 2 * G) : nxt;
+        if (MOM)
+            moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, cur.rb, c0, cnt, n_s, partials);
+        if (has_next)
+            stage_store<T, RPP>(st, nxt, tid, RB, s_col[buf ^ 1], s_val[buf ^ 1], s_row[buf ^ 1]);
+        lds_barrier();
+        buf ^= 1;
+        cur = nxt;
+        nxt = nn;
     }
 }
 
@@ -266,32 +507,108 @@ __global__ __launch_bounds__(256) void k_moment_finalize(const double *__restric
     }
 }
 
+template <int LPR>
+constexpr int rows_per_block()
+{
+    return 4 * (64 / LPR);
+}
+
+// Row blocks of one launch: a workgroup covers min(C, 4*64/LPR) rows of one chunk.
+int64_t sell_row_blocks(const Sell &S, int lpr)
+{
+    const int rpp = 4 * (64 / lpr);
+    const int rb = S.C < rpp ? S.C : rpp;
+    return S.nchunks * (S.C / rb);
+}
+
+// Launch geometry shared by both SELL kernels.
+struct SellGeom {
+    int RB, lg_bpc, lg_xg, order;
+    uint32_t nrb, nslab;
+    const int32_t *sched;
+};
+
+template <int LPR, int NB>
+int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom &g)
+{
+    constexpr int SW = LPR * NB;
+    constexpr int RPP = rows_per_block<LPR>();
+    const int64_t nslab = (a.n_s + SW - 1) / SW;
+    const int64_t nrb = sell_row_blocks(S, LPR);
+    if (nrb * nslab >= ((int64_t)1 << 31) || a.ld * 16 >= ((int64_t)1 << 32))
+        return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
+    g.RB = S.C < RPP ? S.C : RPP;
+    g.lg_bpc = ilog2(S.C / g.RB);
+    // order 2 follows the matrix's chunk schedule (if it has one) slab-major
+    g.order = ctx->tune_order == 1 ? 1 : 0;
+    g.sched = ctx->tune_order == 2 ? S.sched : nullptr;
+    // default placement: the row blocks of one chunk share an XCD; under a
+    // schedule, one locality group of chunks does
+    int grp = S.C / g.RB;
+    if (g.sched && S.sched_group > 0) grp *= S.sched_group;
+    g.lg_xg = ilog2(ctx->tune_xcd_group ? ctx->tune_xcd_group : grp);
+    g.nrb = (uint32_t)nrb;
+    g.nslab = (uint32_t)nslab;
+    return CHEBFD_OK;
+}
+
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
+void launch_sell_k(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
+{
+    const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
+    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB>),
+                       dim3(g.nrb * g.nslab), dim3(256), 0, ctx->stream, S.chunk_ptr,
+                       S.chunk_len, g.sched, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
+                       (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
+                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.order,
+                       g.nslab, g.lg_xg);
+}
+
+// Persistent launch: as many workgroups as fit on the device at once (a
+// multiple of the XCD count), each walking its sequence of blocks.
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, int GB>
+void launch_sell_pipe(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
+{
+    const auto kern = k_step_sell_pipe<T, LPR, NB, MODE, MOM, NT, GB>;
+    static int per_cu = 0;   // resident workgroups per CU of this instantiation
+    if (!per_cu) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kern, 256, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int64_t total = (int64_t)g.nrb * g.nslab;
+    int64_t grid = (int64_t)ctx->num_cu * per_cu / NUM_XCD * NUM_XCD;
+    if (grid > total) grid = total;
+    if (grid < 1) grid = 1;
+    const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, ctx->stream, S.chunk_ptr,
+                       S.chunk_len, g.sched, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
+                       (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
+                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.order,
+                       g.nslab, g.lg_xg);
+}
+
 template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT>
 int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
 {
-    constexpr int SW = LPR * NB;
-    const int64_t nslab = (a.n_s + SW - 1) / SW;
-    const int64_t grid = S.nchunks * nslab;
-    const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    // every chunk fits in LDS -> staged variant, else direct index stream
-    if ((int64_t)S.max_len * S.C <= LDS_ENTRIES && ctx->tune_gathers == 16)
-        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true, 16>), dim3((unsigned)grid),
-                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
-                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
-                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
-                           a.partials, ctx->tune_order, nslab);
-    else if ((int64_t)S.max_len * S.C <= LDS_ENTRIES)
-        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, true, 8>), dim3((unsigned)grid),
-                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
-                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
-                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
-                           a.partials, ctx->tune_order, nslab);
+    SellGeom g;
+    if (int rc = sell_geom<LPR, NB>(ctx, S, a, g)) return rc;
+    // rows that fit the LDS stage -> staged variant (persistent and
+    // pipelined by default), else the index stream
+    const bool staged = S.max_len <= LS;
+    if (staged && ctx->tune_pipeline && ctx->tune_gathers == 8)
+        launch_sell_pipe<T, LPR, NB, MODE, MOM, NT, 8>(ctx, S, a, g);
+    else if (staged && ctx->tune_pipeline)
+        launch_sell_pipe<T, LPR, NB, MODE, MOM, NT, 16>(ctx, S, a, g);
+    else if (staged && ctx->tune_gathers == 8)
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 8>(ctx, S, a, g);
+    else if (staged)
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16>(ctx, S, a, g);
     else
-        hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, false, 8>), dim3((unsigned)grid),
-                           dim3(256), 0, ctx->stream, S.chunk_ptr, S.chunk_len, S.perm, S.col,
-                           val, S.C, S.nchunks, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
-                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
-                           a.partials, ctx->tune_order, nslab);
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, false, 8>(ctx, S, a, g);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }
@@ -350,10 +667,25 @@ int launch_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a, int6
 {
     if (H->storage == CHEBFD_STORAGE_STENCIL) return launch_stencil_step(ctx, H, a, n_part);
     const Sell &S = H->sell;
-    if (n_part) *n_part = S.nchunks;
-    if (a.precision == CHEBFD_PREC_C128)
-        return launch_sell_lpr<double, 1>(ctx, S, a, pick_lpr(ctx, a.n_s, 1));
-    return launch_sell_lpr<float, 2>(ctx, S, a, pick_lpr(ctx, a.n_s, 2));
+    const int nb = a.precision == CHEBFD_PREC_C128 ? 1 : 2;
+    const int lpr = pick_lpr(ctx, a.n_s, nb);
+    if (n_part) *n_part = sell_row_blocks(S, lpr);
+    if (a.precision == CHEBFD_PREC_C128) return launch_sell_lpr<double, 1>(ctx, S, a, lpr);
+    return launch_sell_lpr<float, 2>(ctx, S, a, lpr);
+}
+
+int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                            int64_t n_s)
+{
+    const int nb = precision == CHEBFD_PREC_C128 ? 1 : 2;
+    const int lpr = pick_lpr(ctx, n_s, nb);
+    if (H->storage == CHEBFD_STORAGE_SELL) return sell_row_blocks(H->sell, lpr);
+    // the larger of the two stencil block counts (site-linear and z-march)
+    const Stencil &T = H->st;
+    const int64_t spb = 4 * (64 / lpr);
+    const int64_t lin = (H->n / 4 + spb - 1) / spb;
+    const int64_t zm = (T.L[0] + spb - 1) / spb * T.L[1] * T.L[2];
+    return lin > zm ? lin : zm;
 }
 
 int launch_moment_finalize(chebfd_ctx *ctx, const double *partials, int64_t n_part,

@@ -93,7 +93,8 @@ void free_matrix(chebfd_matrix *H)
 {
     Sell &S = H->sell;
     for (void *p : {(void *)S.chunk_ptr, (void *)S.chunk_len, (void *)S.perm, (void *)S.col,
-                    (void *)S.val64, (void *)S.val32, (void *)H->st.pot64, (void *)H->st.pot32})
+                    (void *)S.val64, (void *)S.val32, (void *)S.sched, (void *)H->st.pot64,
+                    (void *)H->st.pot32})
         if (p) (void)hipFree(p);
 }
 
@@ -183,6 +184,33 @@ int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn)
     return CHEBFD_OK;
 }
 
+// Lattice traversal order of the chunks of a TI matrix: chunks are keyed by
+// the site of their first row as (y, x-run, z) with z fastest, so that
+// consecutive scheduled chunks are z-neighbours and a z-column of chunks
+// forms one locality group.
+int build_ti_schedule(chebfd_matrix *H, const int L[3])
+{
+    Sell &S = H->sell;
+    const int64_t run = std::max(1, S.C / 4);
+    const int64_t nxb = (L[0] + run - 1) / run;
+    std::vector<int64_t> key(S.nchunks);
+    std::vector<int32_t> perm((size_t)S.nchunks * S.C);
+    CHEBFD_HIP(hipMemcpy(perm.data(), S.perm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < S.nchunks; ++c) {
+        int64_t i = -1;
+        for (int r = 0; r < S.C && i < 0; ++r) i = perm[c * S.C + r];
+        if (i < 0) i = 0;
+        const int64_t site = i / 4, x = site % L[0], y = (site / L[0]) % L[1],
+                      z = site / ((int64_t)L[0] * L[1]);
+        key[c] = ((y * nxb + x / run) * L[2] + z);
+    }
+    std::vector<int32_t> order(S.nchunks);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    S.sched_group = L[2];
+    return upload(&S.sched, order);
+}
+
 }  // namespace
 
 }  // namespace chebfd
@@ -263,6 +291,7 @@ extern "C" int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc
     int rc = CHEBFD_OK;
     if (storage == CHEBFD_STORAGE_SELL) {
         rc = build_sell(H, n, sell_C, sell_sigma, rowfn);
+        if (rc == CHEBFD_OK) rc = build_ti_schedule(H, L);
     } else {
         Stencil &S = H->st;
         S.L[0] = Lx;

@@ -131,6 +131,91 @@ def test_filter_c64_vs_reference(env, orc, storage):
     assert relerr(got, ref) < tol
 
 
+@pytest.mark.parametrize("kind", ["ti", "csr"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_filter_many_blocks_per_workgroup(env, orc, kind, prec, pipeline):
+    """Large enough that every persistent workgroup of the pipelined SELL
+    kernel walks many row blocks (tens of thousands of blocks for about a
+    thousand resident workgroups), with a ragged last chunk and moments on;
+    the default one-block-per-workgroup kernel on the same inputs."""
+    torch, B, ctx = env
+    B.chebfd_set_tuning(ctx, "pipeline", pipeline)
+    if kind == "ti":
+        L = (24, 24, 23)
+        Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=6)
+        H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=6, storage=B.STORAGE_SELL)
+    else:
+        n = 50021
+        rp, col, val = inp.random_hermitian_csr(n, seed=9, min_row=2, max_row=28)
+        Hr = orc.CSR(n, rp, col, val)
+        H = B.Matrix.from_csr(ctx, rp, col, val, sell_C=32, sell_sigma=256)
+    a, b = orc.gershgorin(Hr)
+    n_s, n_p = 64, 5
+    X = inp.random_block(Hr.n, n_s, seed=12)
+    if prec == "c64":
+        X = X.astype(np.complex64).astype(np.complex128)
+    gam = inp.random_gamma(n_p, seed=4)
+    ref, mref = orc.filter_block(Hr, a, b, gam, X, moments=True)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    Xd = to_dev(torch, X, dtype=dt)
+    Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
+    mom = torch.zeros((2 * n_p + 1, n_s), dtype=torch.float64, device="cuda")
+    try:
+        B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom)
+        torch.cuda.synchronize()
+    finally:
+        B.chebfd_set_tuning(ctx, "pipeline", 0)
+    got = Xd.cpu().numpy().astype(np.complex128)
+    m = mom.cpu().numpy()
+    if prec == "c128":
+        assert relerr(got, ref) < 1e-12 * n_p
+        assert np.abs(m - mref).max() < 1e-11 * np.abs(mref[0]).max() * n_p
+    else:
+        assert relerr(got, ref) < 30 * math.sqrt(n_p) * 2.0 ** -24
+        assert np.abs(m - mref).max() < 1e-4 * np.abs(mref[0]).max()
+
+
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+def test_launch_settings_give_identical_blocks(env, storage):
+    """Every launch setting computes each output element with the same
+    operations in the same order, so the filtered blocks agree bit for bit;
+    the moment sums (reduced over a setting-dependent tree) agree to
+    rounding."""
+    torch, B, ctx = env
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    L = (16, 16, 15)
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=3, storage=st)
+    info = H.info()
+    a, b = info["g_lo"], info["g_hi"]
+    n_s, n_p = 96, 7
+    X0 = to_dev(torch, inp.random_block(info["n"], n_s, seed=5))
+    gam = inp.random_gamma(n_p, seed=6)
+    settings = [dict(), dict(lanes=64), dict(lanes=16), dict(order=1), dict(xcd_group=1),
+                dict(xcd_group=8, order=1), dict(gathers=8), dict(pipeline=1),
+                dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
+                dict(order=2, pipeline=1, xcd_group=4)]
+    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0)
+    outs, moms = [], []
+    try:
+        for cfg in settings:
+            for k, v in {**defaults, **cfg}.items():
+                B.chebfd_set_tuning(ctx, k, v)
+            Xd = X0.clone()
+            Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
+            mom = torch.zeros((2 * n_p + 1, n_s), dtype=torch.float64, device="cuda")
+            B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom)
+            torch.cuda.synchronize()
+            outs.append(Xd.cpu().numpy())
+            moms.append(mom.cpu().numpy())
+    finally:
+        for k, v in defaults.items():
+            B.chebfd_set_tuning(ctx, k, v)
+    for cfg, o, m in zip(settings, outs, moms):
+        assert np.array_equal(o, outs[0]), cfg
+        assert np.abs(m - moms[0]).max() < 1e-12 * np.abs(moms[0][0]).max(), cfg
+
+
 def test_filter_full_block_equals_column_subset(env, orc):
     """Columns are independent: the 256-column launch (the throughput
     configuration's shape) gives bitwise the same columns as narrower
