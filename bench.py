@@ -65,9 +65,11 @@ def measured_traffic(storage, precision, workload):
     return t
 
 
-def cpu_baseline(workload, n_steps=3):
-    """The CPU reference's filter (plain CSR, OpenMP static) on the same
-    lattice and block width, timed on the host cores."""
+def cpu_baseline(workload, target_s=15.0, max_steps=400):
+    """The CPU reference's filter (plain CSR, OpenMP static over the host
+    threads) on the same lattice and block width, timed on the host cores.
+    The number of recurrence steps is chosen from a two-step probe so that
+    the timed sample takes about target_s seconds."""
     import oracle
     w = inp.WORKLOADS[workload]
     L = w["L"]
@@ -75,6 +77,10 @@ def cpu_baseline(workload, n_steps=3):
     a, b = oracle.gershgorin(H)
     n_s = w["n_s"]
     X = inp.random_block(H.n, n_s, seed=1)
+    t0 = time.perf_counter()
+    oracle.filter_block(H, a, b, oracle.gamma(-w["delta"], w["delta"], a, b, 2), X)
+    per_step = (time.perf_counter() - t0) / 2
+    n_steps = int(min(max_steps, max(3, target_s / max(per_step, 1e-6))))
     gam = oracle.gamma(-w["delta"], w["delta"], a, b, n_steps)
     t0 = time.perf_counter()
     oracle.filter_block(H, a, b, gam, X)
@@ -82,9 +88,35 @@ def cpu_baseline(workload, n_steps=3):
     vb = H.nnz * 20 + 5 * H.n * n_s * 16
     return dict(value=round(n_steps * vb / dt / 1e9, 3), unit="GB/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=f"filter of degree {n_steps} ({n_steps} recurrence steps of Fig. "
-                       f"fig:ChebFD) on the full {L[0]}x{L[1]}x{L[2]} lattice, n_s={n_s}, c128, "
-                       f"{dt:.1f} s; same per-step byte count as the GPU figure")
+                sample=f"filter of degree {n_steps} ({n_steps} fused recurrence steps of Fig. "
+                       f"fig:ChebFD, CSR, OpenMP static) on the full {L[0]}x{L[1]}x{L[2]} lattice, "
+                       f"n_s={n_s}, c128, {dt:.1f} s on {oracle.num_threads()} threads; same "
+                       f"per-step byte count as the GPU figure")
+
+
+def time_fused(B, ctx, H, prec, n_s, delta, steps):
+    """Average duration of one fused MODE_STEP launch, from HIP events
+    recorded on the library's stream around `steps` launches."""
+    import torch
+    info = H.info()
+    a, b = info["g_lo"], info["g_hi"]
+    dt = torch.complex128 if prec == B.PREC_C128 else torch.complex64
+    X = torch.empty((info["n"], n_s), dtype=dt, device="cuda")
+    U = torch.empty_like(X)
+    W = torch.empty_like(X)
+    B.chebfd_random_block(ctx, X, seed=7)
+    gam = B.chebfd_coeffs(-delta, delta, a, b, steps)
+    B.chebfd_filter_apply(ctx, H, gam[:3], a, b, X, U, W)   # warm-up
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    B.chebfd_filter_apply(ctx, H, gam, a, b, X, U, W)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    del X, U, W
+    torch.cuda.empty_cache()
+    return ev0.elapsed_time(ev1) / 1e3 / steps
 
 
 def main():
@@ -98,6 +130,8 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the bandwidth probe and the timed fused launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-storage", action="store_true",
+                    help="skip the fused-kernel timing (and solve) of the other storage")
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="fused launches timed with HIP events for the roofline figure")
     args = ap.parse_args()
@@ -143,24 +177,9 @@ def main():
     n_p, eta = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
 
     # --- the fused kernel alone, timed with HIP events on the library stream
-    dt = torch.complex128 if prec == B.PREC_C128 else torch.complex64
-    X = torch.empty((n, n_s), dtype=dt, device="cuda")
-    U = torch.empty_like(X)
-    W = torch.empty_like(X)
-    B.chebfd_random_block(ctx, X, seed=7)
     ks = args.kernel_steps
-    gam = B.chebfd_coeffs(-delta, delta, a, b, ks)
-    B.chebfd_filter_apply(ctx, H, gam[:3], a, b, X, U, W)   # warm-up
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    B.chebfd_filter_apply(ctx, H, gam, a, b, X, U, W)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_launch = ev0.elapsed_time(ev1) / 1e3 / ks
+    t_launch = time_fused(B, ctx, H, prec, n_s, delta, ks)
     kern_gbs = vb / t_launch / 1e9
-    del X, U, W
-    torch.cuda.empty_cache()
     print(f"# fused launch {t_launch * 1e6:.1f} us = {kern_gbs:.0f} GB/s", flush=True)
 
     traffic = measured_traffic(args.storage, args.precision, args.workload)
@@ -213,6 +232,32 @@ def main():
                             for k, v in stats.items()},
             "fused_kernel_tflops": round(step_flops(n, n_s, nnz_row) / t_launch / 1e12, 3),
         })
+    # the other storage of the same lattice: matrix-free stencil (or SELL)
+    if not args.no_other_storage:
+        other = "stencil" if args.storage == "sell" else "sell"
+        Ho = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0],
+                         storage=B.STORAGE_STENCIL if other == "stencil" else B.STORAGE_SELL,
+                         sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
+        io = Ho.info()
+        mbo = io["matrix_bytes_c128"] if prec == B.PREC_C128 else io["matrix_bytes_c64"]
+        vbo = mbo + 5 * n * n_s * s_d
+        to = time_fused(B, ctx, Ho, prec, n_s, delta, ks)
+        extra = {"storage": other, "algorithmic_bytes_per_launch": int(vbo),
+                 "avg_launch_us": round(to * 1e6, 2), "achieved_gbs": round(vbo / to / 1e9, 1),
+                 "frac": round(vbo / to / 1e9 / HBM_PEAK_GBS, 4)}
+        if not args.kernel_only:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r2 = B.chebfd_solve(ctx, Ho, params)
+            torch.cuda.synchronize()
+            extra["time_to_solution_s"] = round(time.perf_counter() - t0, 4)
+            extra["eigenpairs_found"] = int(len(r2[1]))
+            extra["max_residual"] = float(r2[2].max()) if len(r2[2]) else None
+            extra["same_eigenvalues"] = bool(len(r2[1]) == len(res[1]) and (
+                len(r2[1]) == 0 or np.abs(r2[1] - res[1]).max() < 1e-10 * max(abs(a), abs(b))))
+        out["other_storage"] = extra
+        del Ho
+        print(f"# {other}: fused launch {to * 1e6:.1f} us = {vbo / to / 1e9:.0f} GB/s", flush=True)
     out["roofline"] = roof
     out["bandwidth_probe_gbs"] = {"read_only": round(probe[0], 1), "copy": round(probe[1], 1),
                                   "stream_3r2w": round(probe[2], 1)}

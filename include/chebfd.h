@@ -358,8 +358,14 @@ typedef struct {
     const double *gamma_corr; /* NULL or host array of n_p + 1 multiplicative
                                  corrections: gamma_n <- gamma_n (1 + corr_n) */
     double polish_switch;    /* C64 only: go to FP64 once every in-window
-                                residual is below this or stops improving */
+                                residual below sqrt(eps) is below this, or
+                                they stop improving; NaN = 4 * 2^-23 * S_w
+                                (S_w = max(|a|, |b|)).  The FP64 polish then
+                                filters only the in-window Ritz vectors and
+                                the nearest ones outside the window
+                                (max(n_in + 8, 5 n_in / 4) columns). */
     int vectors;             /* 1: copy the eigenvectors to the host result */
+    int verbose;             /* 1: one progress line per outer iteration on stderr */
 } chebfd_params;
 
 typedef struct {
@@ -375,8 +381,8 @@ typedef struct {
 } chebfd_stats;
 
 /* Fills `p` with defaults: Lanczos kernel mu = 2, eps 1e-9, max_iter 50, C128,
- * lock 1, a = b = NaN, seed 1, polish_switch 1e-6, vectors 1, n_s 32,
- * n_p 200. */
+ * lock 1, a = b = NaN, seed 1, polish_switch NaN, vectors 1, verbose 0,
+ * n_s 32, n_p 200. */
 int chebfd_params_default(chebfd_params *p);
 
 /* Device workspace (bytes) chebfd_solve needs for this matrix and params. */

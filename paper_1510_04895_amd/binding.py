@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("n_p", C.c_int), ("kernel", C.c_int), ("mu", C.c_double), ("eps", C.c_double),
                 ("max_iter", C.c_int), ("precision", C.c_int), ("lock", C.c_int),
                 ("a", C.c_double), ("b", C.c_double), ("seed", C.c_uint64),
-                ("gamma_corr", C.c_void_p), ("polish_switch", C.c_double), ("vectors", C.c_int)]
+                ("gamma_corr", C.c_void_p), ("polish_switch", C.c_double), ("vectors", C.c_int),
+                ("verbose", C.c_int)]
 
 
 class Stats(C.Structure):

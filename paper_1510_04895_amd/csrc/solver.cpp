@@ -21,12 +21,15 @@
 // only the remaining columns are filtered.
 // Precision form (C64): the filter runs on complex64 blocks in FP32; Gram,
 // Rayleigh-Ritz and residuals are FP64 on the FP64-converted block.  When the
-// in-window residuals reach `polish_switch` or stop improving, the block is
-// promoted to complex128 and the FP64 iteration continues to eps.
+// in-window residuals reach `polish_switch` (by default a few FP32 roundings
+// of the spectral scale) or stop improving, the block is promoted to
+// complex128, narrowed to the in-window Ritz vectors and their nearest
+// neighbours, and the FP64 iteration (the polish) continues to eps.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -264,11 +267,12 @@ struct Solver {
         std::vector<double> lock_vals, lock_res;
         std::vector<double> theta, res, S, w;
         int last_active = ns;
+        int ns_act = ns;   // search-space size (the FP64 polish may narrow it)
         std::vector<int> keep_idx, conv_idx;
         const double seps = std::sqrt(p.eps);
         int it;
         for (it = 1; it <= p.max_iter; ++it) {
-            const int k = ns - n_lock;   // active columns
+            const int k = ns_act - n_lock;   // active columns
             last_active = k;
             if (k <= 0) break;
             // ---------------- step 5: filter
@@ -345,6 +349,14 @@ struct Solver {
                 rmin = std::min(rmin, res[j]);
                 if (res[j] <= seps) worst = std::max(worst, res[j]);
             }
+            if (p.verbose) {
+                std::fprintf(stderr,
+                             "chebfd: iteration %d (%s) active %d locked %d converged %d "
+                             "converging %d min in-window residual %.3e filter %.2f s\n",
+                             it, prec == CHEBFD_PREC_C64 ? "c64" : "c128", k, n_lock, nconv,
+                             nconving, rmin, secs(ta, tb));
+                std::fflush(stderr);
+            }
             if (prec == CHEBFD_PREC_C64) {
                 // FP32 phase: switch to FP64 once the in-window residuals sit
                 // below polish_switch or stop improving
@@ -353,7 +365,10 @@ struct Solver {
                     if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= seps)
                         mx = std::max(mx, res[j]);
                 const int ngood = nconv + nconving;
-                const bool below = ngood > 0 && mx <= p.polish_switch;
+                // default threshold: a few FP32 roundings of the spectral scale
+                const double sw = std::max(std::fabs(a), std::fabs(b));
+                const double thr = std::isnan(p.polish_switch) ? 4.0 * 0x1p-23 * sw : p.polish_switch;
+                const bool below = ngood > 0 && mx <= thr;
                 const bool stalled = it >= 2 && ngood > 0 && mx > 0.5 * prev_worst;
                 prev_worst = ngood > 0 ? mx : INFINITY;
                 if (below || stalled) {
@@ -364,6 +379,32 @@ struct Solver {
                         if (bb != X && q < 2) others[q++] = bb;
                     U = others[0];
                     W = others[1];
+                    // the FP64 polish filters the in-window Ritz vectors and
+                    // their nearest neighbours outside the window only:
+                    // max(n_in + 8, 5 n_in / 4) columns (the rest of the
+                    // search space has done its work in the FP32 sweep)
+                    std::vector<int> in_w, out_w;
+                    for (int j = 0; j < k; ++j)
+                        (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi ? in_w : out_w).push_back(j);
+                    const int n_in = (int)in_w.size();
+                    const int m = std::min(k, std::max(n_in + 8, (5 * n_in + 3) / 4));
+                    if (n_in > 0 && m < k) {
+                        auto dist = [&](int j) {
+                            return theta[j] < p.lam_lo ? p.lam_lo - theta[j] : theta[j] - p.lam_hi;
+                        };
+                        std::stable_sort(out_w.begin(), out_w.end(),
+                                         [&](int x, int y) { return dist(x) < dist(y); });
+                        std::vector<int32_t> sel(in_w.begin(), in_w.end());
+                        sel.insert(sel.end(), out_w.begin(), out_w.begin() + (m - n_in));
+                        std::sort(sel.begin(), sel.end());
+                        if ((rc = up(dIdx, sel.data(), sel.size() * 4))) return rc;
+                        if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, X, ns, U, ns, 0, dIdx,
+                                                     n, (int64_t)m)))
+                            return rc;
+                        if ((rc = sync())) return rc;
+                        std::swap(X, U);
+                        ns_act = m;
+                    }
                     // the count to confirm is the number of in-window pairs
                     // the FP32 sweep brought below sqrt(eps)
                     prev_conv = ngood;
@@ -411,7 +452,7 @@ struct Solver {
             }
             prev_conv = total_conv;
             prev_rmin = rmin;
-            if (p.lock && n_lock >= ns) {
+            if (p.lock && n_lock >= ns_act) {
                 status = CHEBFD_WARN_SEARCH_SPACE_TOO_SMALL;
                 break;
             }
@@ -509,8 +550,9 @@ extern "C" int chebfd_params_default(chebfd_params *p)
     p->b = NAN;
     p->seed = 1;
     p->gamma_corr = nullptr;
-    p->polish_switch = 1e-6;
+    p->polish_switch = NAN;
     p->vectors = 1;
+    p->verbose = 0;
     return CHEBFD_OK;
 }
 

@@ -53,10 +53,11 @@ def problem(ctx, seed, L=L_DEFAULT, storage=B.STORAGE_STENCIL):
                 ns0=ns0, np0=np0)
 
 
-def run_solve(ctx, H, delta, n_s, n_p, corr=None, precision=B.PREC_C128, max_iter=40, seed=1):
+def run_solve(ctx, H, delta, n_s, n_p, corr=None, precision=B.PREC_C128, max_iter=40, seed=1,
+              verbose=0):
     p = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p, eps=1e-9,
                          max_iter=max_iter, precision=precision, lock=1, seed=seed, vectors=0,
-                         gamma_corr=corr)
+                         gamma_corr=corr, verbose=verbose)
     t0 = time.perf_counter()
     rc, ev, rs, _, st = B.chebfd_solve(ctx, H, p)
     dt = time.perf_counter() - t0
@@ -208,10 +209,28 @@ def load_model(ctx, path):
     return net
 
 
-def predict(ctx, net, P, n_s_fixed=0):
+def gate_corrections(P, n_p, n_s, corr):
+    """The plain expansion is the fallback: corrections are kept only if
+    they lower the damping factor sigma (Sec. 2.3) of the filter for the
+    rule's search interval at this (N_p, N_S); returns corr or None."""
+    if corr is None or not np.any(corr):
+        return None
+    mu = np.asarray(P["mu"][:N_MOM], np.float64)
+    a, b, d = P["a"], P["b"], P["delta"]
+    ns_max = max(NS_MAX, int(n_s))
+    margin = B.chebfd_dos_params(mu, int(P["n"]), a, b, -d, d, n_s=int(n_s), ns_max=ns_max,
+                                 with_margin=True)[3]
+    g = B.chebfd_coeffs(-d, d, a, b, int(n_p))
+    s_plain = B.chebfd_filter_quality(g, a, b, -d, d, -d - margin, d + margin)[0]
+    s_corr = B.chebfd_filter_quality(g * (1.0 + corr), a, b, -d, d, -d - margin, d + margin)[0]
+    return corr if s_corr < s_plain else None
+
+
+def predict(ctx, net, P, n_s_fixed=0, gate=True):
     """(n_p, n_s, corrections) from the network for problem P; with a fixed
     N_S the rule is re-evaluated for that N_S and only the degree ratio and
-    the corrections are taken from the network."""
+    the corrections are taken from the network.  With gate, corrections
+    that do not improve the filter's damping factor are dropped."""
     import torch
     Y = net.forward(torch.from_numpy(P["feats"][None, :]).cuda()).cpu().numpy()[0]
     np_ref, ns_ref = P["np0"], P["ns0"]
@@ -220,7 +239,11 @@ def predict(ctx, net, P, n_s_fixed=0):
                                                 P["delta"], n_s=n_s_fixed, ns_max=max(NS_MAX, n_s_fixed))
         Y = Y.copy()
         Y[1] = 0.0
-    return B.chebfd_learned_decode(Y, np_ref, ns_ref, N_HAT, C_MAX, ns_max=max(NS_MAX, n_s_fixed))
+    n_p, n_s, corr = B.chebfd_learned_decode(Y, np_ref, ns_ref, N_HAT, C_MAX,
+                                             ns_max=max(NS_MAX, n_s_fixed))
+    if gate:
+        corr = gate_corrections(P, n_p, n_s, corr)
+    return n_p, n_s, corr
 
 
 def evaluate(out_path, model_path, seeds):

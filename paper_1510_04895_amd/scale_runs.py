@@ -30,13 +30,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def window_for_count(mu, n, a, b, n_target, n_s):
-    """delta with N_T(delta) = n_target from the KPM estimate (bisection)."""
+N_MOM_COUNT = 4096   # moments for the eigenvalue count (resolution ~ pi S_w / M)
+
+
+def kpm_count(mu, n, a, b, delta):
+    """N_T = N sum_m g_m c_m mu_m for the window [-delta, delta] with the
+    Jackson kernel (Eq. DOS:target)."""
+    g = B.chebfd_coeffs(-delta, delta, a, b, len(mu) - 1, "jackson")
+    return n * float(np.dot(g, mu))
+
+
+def window_for_count(mu, n, a, b, n_target):
+    """delta with N_T(delta) = n_target (bisection on the KPM count)."""
     lo, hi = 1e-6, 0.5 * (b - a)
-    for _ in range(50):
+    for _ in range(60):
         mid = 0.5 * (lo + hi)
-        nt = B.chebfd_dos_params(mu, n, a, b, -mid, mid, n_s=n_s, ns_max=max(n_s, 2))[0]
-        if nt < n_target:
+        if kpm_count(mu, n, a, b, mid) < n_target:
             lo = mid
         else:
             hi = mid
@@ -52,6 +61,8 @@ def main():
     ap.add_argument("--storage", default="stencil", choices=["sell", "stencil"])
     ap.add_argument("--forms", default="fp64,c64,c64_learned")
     ap.add_argument("--max-iter", type=int, default=40)
+    ap.add_argument("--plan-only", action="store_true",
+                    help="only the window, the rule's N_p and the fused-step time per precision")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1510_04895_amd", "models",
                                                      "ti_32x32x16_mlp.npz"))
     args = ap.parse_args()
@@ -63,14 +74,38 @@ def main():
     H = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st)
     info = H.info()
     n, a, b = info["n"], info["g_lo"], info["g_hi"]
-    mu = B.chebfd_kpm_moments(ctx, H, learned.N_VEC, learned.N_MOM, w["seeds"][0], a, b,
-                              precision=B.PREC_C64)
-    delta = window_for_count(mu, n, a, b, w["n_target"], n_s)
-    nt, _, np_rule, margin = B.chebfd_dos_params(mu, n, a, b, -delta, delta, n_s=n_s,
-                                                  ns_max=n_s, with_margin=True)
+    mu_c = B.chebfd_kpm_moments(ctx, H, learned.N_VEC, N_MOM_COUNT, w["seeds"][0], a, b,
+                                precision=B.PREC_C64)
+    mu = mu_c[:learned.N_MOM]
+    delta = window_for_count(mu_c, n, a, b, w["n_target"])
+    nt = kpm_count(mu_c, n, a, b, delta)
+    _, _, np_rule, margin = B.chebfd_dos_params(mu, n, a, b, -delta, delta, n_s=n_s,
+                                                 ns_max=n_s, with_margin=True)
     print(json.dumps(dict(workload=args.workload, N=n, a=a, b=b, delta=delta, nt_est=nt,
                           np_rule=np_rule, margin=margin,
                           setup_s=round(time.perf_counter() - t0, 2))), flush=True)
+    if args.plan_only:
+        import torch
+        plan = dict(workload=args.workload, N=n, delta=delta, nt_est=nt, np_rule=np_rule)
+        for name, prec, dt in (("c128", B.PREC_C128, torch.complex128),
+                               ("c64", B.PREC_C64, torch.complex64)):
+            X = torch.empty((n, n_s), dtype=dt, device="cuda")
+            U, Wb = torch.empty_like(X), torch.empty_like(X)
+            B.chebfd_random_block(ctx, X, seed=1)
+            g = B.chebfd_coeffs(-delta, delta, a, b, 12)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.chebfd_filter_apply(ctx, H, g, a, b, X, U, Wb)
+            torch.cuda.synchronize()
+            step = (time.perf_counter() - t0) / 12
+            plan[f"step_ms_{name}"] = round(step * 1e3, 2)
+            plan[f"filter_pass_s_{name}"] = round(step * np_rule, 1)
+            del X, U, Wb
+            torch.cuda.empty_cache()
+        print(json.dumps(plan), flush=True)
+        with open(args.out, "w") as fh:
+            json.dump(plan, fh, indent=1)
+        return
     P = dict(H=H, n=n, a=a, b=b, delta=delta, mu=mu,
              feats=B.chebfd_learned_features(mu, a, b, -delta, delta), nt=nt, ns0=n_s,
              np0=np_rule)
@@ -84,8 +119,9 @@ def main():
             n_p, _, corr = learned.predict(ctx, net, P, n_s_fixed=n_s)
         torch.cuda.synchronize()
         r = learned.run_solve(ctx, H, delta, n_s, n_p, corr=corr, precision=prec,
-                              max_iter=args.max_iter, seed=w["seeds"][0])
-        row = dict(form=form, n_p=n_p, status=r["rc"], found=r["found"], time_s=r["time"],
+                              max_iter=args.max_iter, seed=w["seeds"][0], verbose=1)
+        row = dict(form=form, n_p=n_p, corrections=corr is not None, status=r["rc"],
+                   found=r["found"], time_s=r["time"],
                    n_mvm=r["n_mvm"], iterations=r["iterations"],
                    max_residual=float(r["res"].max()) if r["found"] else None)
         if form == "fp64":

@@ -1,0 +1,95 @@
+"""Parity at the full 64x64x32 size (N = 524,288, 256 search vectors) in the
+launch configuration the benchmark times: the fused filter against the CPU
+reference on the whole block, and the complete solve checked through
+properties the reference recomputes at any size (residuals from its own
+sparse product, orthonormality, count and Kramers degeneracy)."""
+import math
+
+import numpy as np
+import pytest
+
+import chebfd_inputs as inp
+
+pytestmark = pytest.mark.gpu
+
+W = inp.WORKLOADS["ti_64x64x32"]
+
+
+@pytest.fixture(scope="module")
+def env(orc):
+    import torch
+    from paper_1510_04895_amd import binding as B
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    Hr = orc.ti_hamiltonian(*W["L"], pbc=W["pbc"], V=W["V"], seed=W["seeds"][0])
+    return torch, B, ctx, Hr
+
+
+def _matrix(B, ctx, storage):
+    return B.Matrix.ti(ctx, W["L"], pbc=W["pbc"], V=W["V"], seed=W["seeds"][0],
+                       storage=B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL,
+                       sell_C=W["sell_C"], sell_sigma=W["sell_sigma"])
+
+
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_fused_filter_full_size(env, orc, storage, prec):
+    torch, B, ctx, Hr = env
+    a, b = orc.gershgorin(Hr)
+    n_s, n_p = W["n_s"], 4
+    X = inp.random_block(Hr.n, n_s, seed=21)
+    if prec == "c64":
+        X = X.astype(np.complex64).astype(np.complex128)
+    gam = orc.gamma(-W["delta"], W["delta"], a, b, n_p)
+    ref = orc.filter_block(Hr, a, b, gam, X)
+    H = _matrix(B, ctx, storage)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    Xd = torch.from_numpy(X).to(dt).cuda()
+    Ud, Wd = torch.empty_like(Xd), torch.empty_like(Xd)
+    B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
+    torch.cuda.synchronize()
+    got = Xd.cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    tol = 1e-12 * n_p if prec == "c128" else 30 * math.sqrt(n_p) * 2.0 ** -24
+    assert err < tol, err
+
+
+def test_solve_full_size(env, orc):
+    """The benchmark's solve (SELL-32-256, FP64, N_S 256, window holding 64
+    eigenvalues): every returned pair has a residual <= 1e-9 when the
+    reference recomputes H v - lambda v, the vectors are orthonormal, the
+    eigenvalues lie in the window and come in Kramers pairs, and the
+    matrix-free storage finds the same eigenvalues."""
+    torch, B, ctx, Hr = env
+    d = W["delta"]
+    out = {}
+    for storage in ("sell", "stencil"):
+        H = _matrix(B, ctx, storage)
+        info = H.info()
+        a, b = info["g_lo"], info["g_hi"]
+        dp = d * (math.sqrt(W["n_s"] / W["n_target"]) - 1.0)
+        n_p, _ = B.chebfd_optimal_np(a, b, -d, d, -d - dp, d + dp)
+        p = B.default_params(lam_lo=-d, lam_hi=d, n_s=W["n_s"], n_p=n_p, kernel=W["kernel"],
+                             mu=W["mu"], eps=W["eps"], max_iter=60, lock=1,
+                             seed=W["seeds"][0], vectors=1 if storage == "sell" else 0)
+        out[storage] = B.chebfd_solve(ctx, H, p)
+        del H
+        torch.cuda.empty_cache()
+    rc, ev, rs, V, stats = out["sell"]
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0, stats
+    assert ev.size == W["n_target"]
+    assert np.all(np.abs(ev) <= d) and np.all(np.diff(ev) >= 0)
+    # residuals recomputed by the reference's own sparse product
+    HV = orc.spmm(Hr, V)
+    r = np.linalg.norm(HV - V * ev, axis=0)
+    assert r.max() <= 1e-9, r.max()
+    assert np.abs(r - rs).max() < 1e-11
+    G = V.conj().T @ V
+    assert np.abs(G - np.eye(ev.size)).max() < 1e-10
+    # time-reversal symmetry: exact Kramers pairs
+    assert np.abs(ev[0::2] - ev[1::2]).max() < 1e-10 * S_w
+    rc2, ev2, rs2, _, _ = out["stencil"]
+    assert rc2 == 0 and ev2.size == ev.size
+    assert np.abs(ev2 - ev).max() < 1e-10 * S_w
+    assert rs2.max() <= 1e-9
