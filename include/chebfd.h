@@ -234,6 +234,8 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *   "pipeline"    SELL only: 0 (default) = one row block per workgroup,
  *                 1 = persistent workgroups that stage the next row block
  *                 while the current one is gathered;
+ *   "batches"     stencil only: the six neighbour sites requested in 1
+ *                 (default) or 2 batches (in-plane, then z);
  *   "xcd_group"   consecutive workgroups placed on one of the 8 XCDs (each
  *                 with its own L2): 1 = hardware round-robin order, a power
  *                 of two up to 64, 0 = default (SELL: the workgroups of one

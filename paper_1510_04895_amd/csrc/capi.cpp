@@ -345,6 +345,7 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     else if (k == "order" && value >= 0 && value <= 2) ctx->tune_order = value;
     else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
     else if (k == "pipeline" && (value == 0 || value == 1)) ctx->tune_pipeline = value;
+    else if (k == "batches" && (value == 1 || value == 2)) ctx->tune_batches = value;
     else if (k == "xcd_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
         ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");

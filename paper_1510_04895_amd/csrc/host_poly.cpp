@@ -3,6 +3,7 @@
 // eta-minimising polynomial degree.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <map>
 #include <vector>
 
@@ -65,22 +66,56 @@ double poly_value(const double *gamma, int n_p, double a, double b, double x)
     return gamma[0] + y * b1 - b2;
 }
 
+// In-place iterative radix-2 complex FFT (length a power of two).
+void fft(std::vector<std::complex<double>> &v)
+{
+    const size_t n = v.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(v[i], v[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const double ang = -2.0 * M_PI / (double)len;
+        const std::complex<double> wl(std::cos(ang), std::sin(ang));
+        for (size_t i = 0; i < n; i += len) {
+            std::complex<double> w(1.0, 0.0);
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> x = v[i + k], y = v[i + k + len / 2] * w;
+                v[i + k] = x + y;
+                v[i + k + len / 2] = x - y;
+                w *= wl;
+            }
+        }
+    }
+}
+
 // sigma = max_{x in [a,b] \ [s_lo,s_hi]} |p| / min_{x in [t_lo,t_hi]} |p|,
-// eta = -n_p / log10 sigma (Sec. 2.3).  |p| is sampled on a grid uniform in
-// theta = acos((2x - a - b)/(b - a)) with 8 points per period of T_{n_p},
-// plus the four interval edges.
+// eta = -n_p / log10 sigma (Sec. 2.3).  |p| is sampled on the grid
+// theta_k = pi k / M, k = 0..M, uniform in theta = acos((2x - a - b)/(b - a)),
+// with M the smallest power of two giving at least 8 points per period of
+// T_{n_p}, plus the four interval edges.  p(cos theta_k) = sum_n gamma_n
+// cos(n theta_k) is a DCT-I, evaluated with one FFT of length 2M of the
+// even extension of gamma: O(n_p log n_p) instead of a Clenshaw sum per point.
 void quality(const double *gamma, int n_p, double a, double b, double t_lo, double t_hi,
              double s_lo, double s_hi, double *sigma, double *eta)
 {
-    const int M = std::max(8 * (n_p + 1) / 2, 64);
+    size_t M = 64;
+    while (M < (size_t)(4 * (n_p + 1))) M <<= 1;
+    std::vector<std::complex<double>> v(2 * M, 0.0);
+    for (int n = 0; n <= n_p; ++n) v[n] = gamma[n];
+    for (int n = 1; n <= n_p; ++n) v[2 * M - n] = gamma[n];
+    fft(v);
     double mx = 0.0, mn = INFINITY;
-    for (int k = 0; k <= M; ++k) {
-        const double th = M_PI * k / M;
+    for (size_t k = 0; k <= M; ++k) {
+        const double th = M_PI * (double)k / (double)M;
         const double x = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(th);
         const bool in_t = x >= t_lo && x <= t_hi;
         const bool out_s = x < s_lo || x > s_hi;
         if (!in_t && !out_s) continue;
-        const double p = std::fabs(poly_value(gamma, n_p, a, b, x));
+        // FFT[k] = gamma_0 + 2 sum_{n>=1} gamma_n cos(n theta_k)
+        const double p = std::fabs(0.5 * (v[k].real() + gamma[0]));
         if (in_t) mn = std::min(mn, p);
         if (out_s) mx = std::max(mx, p);
     }
@@ -143,19 +178,35 @@ extern "C" int chebfd_optimal_np(double a, double b, double t_lo, double t_hi, d
         f[k] = e;
         return e;
     };
-    // eta(n_p) is jagged: scan a 0.5% geometric grid, then every integer
-    // within +-2% of the three best grid points.
+    // eta(n_p) is jagged: scan a 2% geometric grid, refine the five best
+    // points on a 0.25% grid within +-3%, then scan every integer within
+    // +-max(2, 0.5%) of the three best points found so far.
+    auto geometric = [](double lo, double hi, double step, std::vector<int> &out) {
+        for (double x = lo; x <= hi * 1.0000001; x *= step) {
+            const int k = (int)std::lround(x);
+            if (out.empty() || out.back() != k) out.push_back(k);
+        }
+    };
+    auto best_k = [&](size_t cnt) {
+        std::vector<std::pair<double, int>> sc;
+        for (auto &kv : f) sc.push_back({kv.second, kv.first});
+        std::sort(sc.begin(), sc.end());
+        std::vector<int> out;
+        for (size_t i = 0; i < std::min(cnt, sc.size()); ++i) out.push_back(sc[i].second);
+        return out;
+    };
     std::vector<int> grid;
-    for (double x = np_min; x <= np_max * 1.0000001; x *= 1.005) {
-        const int k = (int)std::lround(x);
-        if (grid.empty() || grid.back() != k) grid.push_back(k);
-    }
+    geometric(np_min, np_max, 1.02, grid);
     if (grid.back() != np_max) grid.push_back(np_max);
-    std::vector<std::pair<double, int>> sc;
-    for (int k : grid) sc.push_back({ev(k), k});
-    std::sort(sc.begin(), sc.end());
-    for (size_t i = 0; i < std::min<size_t>(3, sc.size()); ++i) {
-        const int k = sc[i].second, w = std::max(2, (int)(0.02 * k));
+    for (int k : grid) ev(k);
+    for (int k : best_k(5)) {
+        std::vector<int> fine;
+        geometric(std::max<double>(np_min, 0.97 * k), std::min<double>(np_max, 1.03 * k), 1.0025,
+                  fine);
+        for (int j : fine) ev(j);
+    }
+    for (int k : best_k(3)) {
+        const int w = std::max(2, (int)(0.005 * k));
         for (int j = std::max(np_min, k - w); j <= std::min(np_max, k + w); ++j) ev(j);
     }
     int best = np_min;

@@ -79,6 +79,7 @@ struct chebfd_ctx {
     int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
     int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
     int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
+    int tune_batches = 1;   // stencil: neighbour loads in 1 batch or 2 (in-plane, then z)
     int tune_xcd_group = 0; // consecutive workgroups per XCD: 0 = default, 1 = hardware order
 };
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void add_hop(Pack<T, NB> (&acc)[4], const Site<T, NB>
     }
 }
 
-template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT, int NBATCH>
 __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc, T th, T mm,
                                                  const T *__restrict__ pot, int64_t nsites,
                                                  int64_t nblk, const T *__restrict__ u,
@@ -129,17 +129,20 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
         const int yy = (int)(rem / Lx);
         const int x = (int)(rem - (int64_t)yy * Lx);
         const Site<T, NB> uo = load_site<T, NB>(u, site, ld, c0, cnt);
-        // streamed operands of the four output rows, issued before the
-        // neighbour loads they do not depend on
+        // streamed operands of the four output rows, issued with the first
+        // batch (NBATCH = 1) or the second (NBATCH = 2, fewer registers)
         Site<T, NB> wo, yo;
-        if (MODE == MODE_SECOND || MODE == MODE_STEP)
+        auto load_streams = [&]() {
+            if (MODE == MODE_SECOND || MODE == MODE_STEP)
 #pragma unroll
-            for (int o = 0; o < 4; ++o)
-                wo.o[o] = load_pack_n<T, NB, NT>(wold + 2 * ((4 * site + o) * ld + c0), cnt);
-        if (MODE == MODE_STEP)
+                for (int o = 0; o < 4; ++o)
+                    wo.o[o] = load_pack_n<T, NB, NT>(wold + 2 * ((4 * site + o) * ld + c0), cnt);
+            if (MODE == MODE_STEP)
 #pragma unroll
-            for (int o = 0; o < 4; ++o)
-                yo.o[o] = load_pack_n<T, NB, NT>(y + 2 * ((4 * site + o) * ld + c0), cnt);
+                for (int o = 0; o < 4; ++o)
+                    yo.o[o] = load_pack_n<T, NB, NT>(y + 2 * ((4 * site + o) * ld + c0), cnt);
+        };
+        if (NBATCH == 1) load_streams();
         const T vn = pot[site];
         Pack<T, NB> acc[4];
 #pragma unroll
@@ -151,47 +154,60 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                 acc[o].im[e] = d * uo.o[o].im[e];
             }
         }
-        // +-x
+        // The six neighbours, branch-free: a missing neighbour (open
+        // boundary) reads the site itself with hopping weight 0.  All their
+        // rows are requested before the first one is used (NBATCH = 1), or
+        // the in-plane ones first and the z pair second (NBATCH = 2).
+        int64_t nb[6];
+        T tw[6];
         {
-            int xp = x + 1, xm = x - 1;
-            const bool per = pbc & 1;
-            if (xp < Lx || per) {
-                if (xp >= Lx) xp -= Lx;
-                add_hop<T, NB, 0>(acc, load_site<T, NB>(u, site - x + xp, ld, c0, cnt), th, T(1));
-            }
-            if (xm >= 0 || per) {
-                if (xm < 0) xm += Lx;
-                add_hop<T, NB, 0>(acc, load_site<T, NB>(u, site - x + xm, ld, c0, cnt), th, T(-1));
+            const int64_t lxy_ = (int64_t)Lx * Ly;
+            const int co[3] = {x, yy, z};
+            const int Ld[3] = {Lx, Ly, Lz};
+            const int64_t stride[3] = {1, Lx, lxy_};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const bool per = (pbc >> j) & 1;
+                int cp = co[j] + 1, cm = co[j] - 1;
+                const bool okp = cp < Ld[j] || per, okm = cm >= 0 || per;
+                if (cp >= Ld[j]) cp -= Ld[j];
+                if (cm < 0) cm += Ld[j];
+                nb[2 * j] = okp ? site + (int64_t)(cp - co[j]) * stride[j] : site;
+                nb[2 * j + 1] = okm ? site + (int64_t)(cm - co[j]) * stride[j] : site;
+                tw[2 * j] = okp ? th : T(0);
+                tw[2 * j + 1] = okm ? th : T(0);
             }
         }
-        // +-y
-        {
-            int yp = yy + 1, ym = yy - 1;
-            const bool per = (pbc >> 1) & 1;
-            if (yp < Ly || per) {
-                if (yp >= Ly) yp -= Ly;
-                add_hop<T, NB, 1>(acc, load_site<T, NB>(u, site + (int64_t)(yp - yy) * Lx, ld, c0, cnt),
-                                  th, T(1));
+        if (NBATCH == 1) {
+            Site<T, NB> un[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) un[j] = load_site<T, NB>(u, nb[j], ld, c0, cnt);
+            __builtin_amdgcn_sched_barrier(0);
+            add_hop<T, NB, 0>(acc, un[0], tw[0], T(1));
+            add_hop<T, NB, 0>(acc, un[1], tw[1], T(-1));
+            add_hop<T, NB, 1>(acc, un[2], tw[2], T(1));
+            add_hop<T, NB, 1>(acc, un[3], tw[3], T(-1));
+            add_hop<T, NB, 2>(acc, un[4], tw[4], T(1));
+            add_hop<T, NB, 2>(acc, un[5], tw[5], T(-1));
+        } else {
+            {
+                Site<T, NB> un[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) un[j] = load_site<T, NB>(u, nb[j], ld, c0, cnt);
+                __builtin_amdgcn_sched_barrier(0);
+                add_hop<T, NB, 0>(acc, un[0], tw[0], T(1));
+                add_hop<T, NB, 0>(acc, un[1], tw[1], T(-1));
+                add_hop<T, NB, 1>(acc, un[2], tw[2], T(1));
+                add_hop<T, NB, 1>(acc, un[3], tw[3], T(-1));
             }
-            if (ym >= 0 || per) {
-                if (ym < 0) ym += Ly;
-                add_hop<T, NB, 1>(acc, load_site<T, NB>(u, site + (int64_t)(ym - yy) * Lx, ld, c0, cnt),
-                                  th, T(-1));
-            }
-        }
-        // +-z
-        {
-            int zp = z + 1, zm = z - 1;
-            const bool per = (pbc >> 2) & 1;
-            if (zp < Lz || per) {
-                if (zp >= Lz) zp -= Lz;
-                add_hop<T, NB, 2>(acc, load_site<T, NB>(u, site + (int64_t)(zp - z) * lxy, ld, c0, cnt),
-                                  th, T(1));
-            }
-            if (zm >= 0 || per) {
-                if (zm < 0) zm += Lz;
-                add_hop<T, NB, 2>(acc, load_site<T, NB>(u, site + (int64_t)(zm - z) * lxy, ld, c0, cnt),
-                                  th, T(-1));
+            {
+                Site<T, NB> un[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) un[j] = load_site<T, NB>(u, nb[4 + j], ld, c0, cnt);
+                load_streams();
+                __builtin_amdgcn_sched_barrier(0);
+                add_hop<T, NB, 2>(acc, un[0], tw[4], T(1));
+                add_hop<T, NB, 2>(acc, un[1], tw[5], T(-1));
             }
         }
 #pragma unroll
@@ -306,7 +322,9 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     int lg_xg = ilog2(ctx->tune_xcd_group);
     if (order == 2 && !ctx->tune_xcd_group) lg_xg = ilog2(S.L[2]);
     const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
-    hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
+    const auto kern = ctx->tune_batches == 2 ? k_step_ti<T, LPS, NB, MODE, MOM, NT, 2>
+                                             : k_step_ti<T, LPS, NB, MODE, MOM, NT, 1>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nblk * nslab)),
                        dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,
                        (T)(-0.5 * S.t), (T)S.m, pot, nsites, nblk, (const T *)a.u,
                        (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld, (T)a.s_h,

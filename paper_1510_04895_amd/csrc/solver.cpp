@@ -13,8 +13,8 @@
 //    eps < r <= sqrt(eps), a ghost candidate otherwise;
 //  - exit after >= 2 iterations once no in-window pair is converging, the
 //    converged count has not changed, and the smallest remaining in-window
-//    residual has not fallen below half its previous value (ghosts: large
-//    residual that does not decrease);
+//    residual fell by less than 10% (ghosts: a large residual that does
+//    not decrease; a slowly converging pair still gains more);
 //  - the restart block is the set of Ritz vectors.
 // Locking (a refinement the paper lists in Sec. 6): converged in-window
 // pairs move to a locked set Q, later blocks are kept orthogonal to Q and
@@ -264,6 +264,7 @@ struct Solver {
 
         int n_lock = 0, prev_conv = -1, status = CHEBFD_WARN_NOT_CONVERGED;
         double prev_rmin = INFINITY, prev_worst = INFINITY;
+        int prev_good = 0;
         std::vector<double> lock_vals, lock_res;
         std::vector<double> theta, res, S, w;
         int last_active = ns;
@@ -369,8 +370,12 @@ struct Solver {
                 const double sw = std::max(std::fabs(a), std::fabs(b));
                 const double thr = std::isnan(p.polish_switch) ? 4.0 * 0x1p-23 * sw : p.polish_switch;
                 const bool below = ngood > 0 && mx <= thr;
-                const bool stalled = it >= 2 && ngood > 0 && mx > 0.5 * prev_worst;
+                // stalled: the set of good pairs did not grow and their worst
+                // residual no longer halves (the FP32 floor)
+                const bool stalled = it >= 2 && ngood > 0 && ngood <= prev_good &&
+                                     mx > 0.5 * prev_worst;
                 prev_worst = ngood > 0 ? mx : INFINITY;
+                prev_good = ngood;
                 if (below || stalled) {
                     prec = CHEBFD_PREC_C128;   // X (c128 Ritz vectors) continues in FP64
                     void *others[2];
@@ -445,7 +450,7 @@ struct Solver {
                 }
             }
             const int total_conv = p.lock ? n_lock : nconv;
-            const bool stagnant = (rmin == INFINITY) || (rmin >= 0.5 * prev_rmin);
+            const bool stagnant = (rmin == INFINITY) || (rmin >= 0.9 * prev_rmin);
             if (it >= 2 && nconving == 0 && total_conv == prev_conv && stagnant) {
                 status = CHEBFD_OK;
                 break;

@@ -215,7 +215,7 @@ def gate_corrections(P, n_p, n_s, corr):
     rule's search interval at this (N_p, N_S); returns corr or None."""
     if corr is None or not np.any(corr):
         return None
-    mu = np.asarray(P["mu"][:N_MOM], np.float64)
+    mu = np.asarray(P.get("mu_rule", P["mu"][:N_MOM]), np.float64)
     a, b, d = P["a"], P["b"], P["delta"]
     ns_max = max(NS_MAX, int(n_s))
     margin = B.chebfd_dos_params(mu, int(P["n"]), a, b, -d, d, n_s=int(n_s), ns_max=ns_max,
@@ -235,7 +235,8 @@ def predict(ctx, net, P, n_s_fixed=0, gate=True):
     Y = net.forward(torch.from_numpy(P["feats"][None, :]).cuda()).cpu().numpy()[0]
     np_ref, ns_ref = P["np0"], P["ns0"]
     if n_s_fixed:
-        _, ns_ref, np_ref = B.chebfd_dos_params(P["mu"], P["n"], P["a"], P["b"], -P["delta"],
+        mu_rule = P.get("mu_rule", P["mu"])
+        _, ns_ref, np_ref = B.chebfd_dos_params(mu_rule, P["n"], P["a"], P["b"], -P["delta"],
                                                 P["delta"], n_s=n_s_fixed, ns_max=max(NS_MAX, n_s_fixed))
         Y = Y.copy()
         Y[1] = 0.0

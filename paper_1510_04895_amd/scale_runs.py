@@ -79,7 +79,10 @@ def main():
     mu = mu_c[:learned.N_MOM]
     delta = window_for_count(mu_c, n, a, b, w["n_target"])
     nt = kpm_count(mu_c, n, a, b, delta)
-    _, _, np_rule, margin = B.chebfd_dos_params(mu, n, a, b, -delta, delta, n_s=n_s,
+    # the rule's margin from the high-resolution moments: the search
+    # interval must hold N_S eigenvalues, and 256 moments cannot resolve the
+    # small margins of N_S/N_T near 1
+    _, _, np_rule, margin = B.chebfd_dos_params(mu_c, n, a, b, -delta, delta, n_s=n_s,
                                                  ns_max=n_s, with_margin=True)
     print(json.dumps(dict(workload=args.workload, N=n, a=a, b=b, delta=delta, nt_est=nt,
                           np_rule=np_rule, margin=margin,
@@ -106,7 +109,7 @@ def main():
         with open(args.out, "w") as fh:
             json.dump(plan, fh, indent=1)
         return
-    P = dict(H=H, n=n, a=a, b=b, delta=delta, mu=mu,
+    P = dict(H=H, n=n, a=a, b=b, delta=delta, mu=mu, mu_rule=mu_c,
              feats=B.chebfd_learned_features(mu, a, b, -delta, delta), nt=nt, ns0=n_s,
              np0=np_rule)
     results = {}

@@ -194,8 +194,9 @@ def test_launch_settings_give_identical_blocks(env, storage):
     settings = [dict(), dict(lanes=64), dict(lanes=16), dict(order=1), dict(xcd_group=1),
                 dict(xcd_group=8, order=1), dict(gathers=8), dict(pipeline=1),
                 dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
-                dict(order=2, pipeline=1, xcd_group=4)]
-    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0)
+                dict(order=2, pipeline=1, xcd_group=4), dict(batches=2),
+                dict(batches=2, lanes=64)]
+    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1)
     outs, moms = [], []
     try:
         for cfg in settings:
