@@ -33,7 +33,7 @@ import numpy as np  # noqa: E402
 import chebfd_inputs as inp  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h", "dispatch.h"],
+KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h", "dispatch.h", "matrix.cpp"],
                   "stencil": ["kernels_stencil.hip", "pack.h", "dispatch.h"]}
 
 

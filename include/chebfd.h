@@ -234,6 +234,12 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *   "pipeline"    SELL only: 0 (default) = one row block per workgroup,
  *                 1 = persistent workgroups that stage the next row block
  *                 while the current one is gathered;
+ *   "pair_rows"   SELL matrices built on this context: 1 (default) = inside
+ *                 each chunk, rows whose entries gather the same columns at
+ *                 the same positions are placed in adjacent slots (one wave
+ *                 instruction), 0 = length-sorted order only;
+ *   "waves"       SELL only: register budget of the staged kernel for 5
+ *                 (default) or 4 resident waves per SIMD;
  *   "batches"     stencil only: the six neighbour sites requested in 1
  *                 (default) or 2 batches (in-plane, then z);
  *   "xcd_group"   consecutive workgroups placed on one of the 8 XCDs (each
@@ -361,13 +367,15 @@ typedef struct {
                                  corrections: gamma_n <- gamma_n (1 + corr_n) */
     double polish_switch;    /* C64 only: go to FP64 once every in-window
                                 residual below sqrt(eps) is below this, or
-                                they stop improving; NaN = 4 * 2^-23 * S_w
+                                their median stops halving with no new
+                                pair below sqrt(eps); NaN = 4 * 2^-23 * S_w
                                 (S_w = max(|a|, |b|)).  The FP64 polish then
                                 filters only the in-window Ritz vectors and
                                 the nearest ones outside the window
                                 (max(n_in + 8, 5 n_in / 4) columns). */
     int vectors;             /* 1: copy the eigenvectors to the host result */
-    int verbose;             /* 1: one progress line per outer iteration on stderr */
+    int verbose;             /* 1: progress on stderr: one line per outer
+                                iteration and per 1024 filter steps */
 } chebfd_params;
 
 typedef struct {

@@ -1,5 +1,6 @@
 // C ABI: contexts, errors, and the low-level device entry points.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -91,7 +92,7 @@ int check_block(const char *who, int precision, const void *p, int64_t n, int64_
 // The polynomial filter (Fig. fig:ChebFD) on caller buffers.
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom)
+                 double *mom, int progress)
 {
     const double alpha = 2.0 / (b - a), beta = (a + b) / (a - b);
     double *part = nullptr;
@@ -145,6 +146,12 @@ int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double
         if ((rc = launch_step(ctx, H, s, &n_part))) return rc;
         if (mom && (rc = launch_moment_finalize(ctx, part, n_part, n_s, MODE_STEP, k, mom)))
             return rc;
+        if (progress > 0 && k % progress == 0 && k < n_p) {
+            // progress of a long filter pass: the steps up to k have run
+            CHEBFD_HIP(hipStreamSynchronize(ctx->stream));
+            std::fprintf(stderr, "chebfd: filter step %d of %d done\n", k, n_p);
+            std::fflush(stderr);
+        }
     }
     return CHEBFD_OK;
 }
@@ -346,6 +353,8 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
     else if (k == "pipeline" && (value == 0 || value == 1)) ctx->tune_pipeline = value;
     else if (k == "batches" && (value == 1 || value == 2)) ctx->tune_batches = value;
+    else if (k == "waves" && (value == 4 || value == 5)) ctx->tune_waves = value;
+    else if (k == "pair_rows" && (value == 0 || value == 1)) ctx->tune_pair_rows = value;
     else if (k == "xcd_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
         ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");

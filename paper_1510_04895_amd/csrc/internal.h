@@ -79,6 +79,8 @@ struct chebfd_ctx {
     int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
     int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
     int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
+    int tune_pair_rows = 1; // SELL build: pair rows with equal gather columns in a chunk
+    int tune_waves = 5;     // SELL: occupancy target of the staged kernel (waves per SIMD), 4 or 5
     int tune_batches = 1;   // stencil: neighbour loads in 1 batch or 2 (in-plane, then z)
     int tune_xcd_group = 0; // consecutive workgroups per XCD: 0 = default, 1 = hardware order
 };
@@ -145,7 +147,7 @@ int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, 
                        int64_t ldd, int64_t d0, const int32_t *idx_dev, int64_t n, int64_t m);
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom);
+                 double *mom, int progress = 0);
 int check_block(const char *who, int precision, const void *p, int64_t n, int64_t n_s,
                 int64_t ld, bool packed);
 

@@ -352,8 +352,9 @@ __device__ __forceinline__ void moment_partials(double (&m0)[NB], double (&m1)[N
 
 // One row block per workgroup (used for rows longer than the LDS stage,
 // which read the index stream directly, and as a tuning alternative).
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
-__global__ __launch_bounds__(256) void k_step_sell(
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB,
+          int WAVES = 4>
+__global__ __launch_bounds__(256, WAVES) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ sched, const int32_t *__restrict__ perm,
     const int32_t *__restrict__ col,
@@ -552,11 +553,12 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
     return CHEBFD_OK;
 }
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB,
+          int WAVES = 4>
 void launch_sell_k(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
 {
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB>),
+    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB, WAVES>),
                        dim3(g.nrb * g.nslab), dim3(256), 0, ctx->stream, S.chunk_ptr,
                        S.chunk_len, g.sched, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
                        (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
@@ -605,6 +607,8 @@ int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
         launch_sell_pipe<T, LPR, NB, MODE, MOM, NT, 16>(ctx, S, a, g);
     else if (staged && ctx->tune_gathers == 8)
         launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 8>(ctx, S, a, g);
+    else if (staged && ctx->tune_waves == 5)
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16, 5>(ctx, S, a, g);
     else if (staged)
         launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16>(ctx, S, a, g);
     else

@@ -100,7 +100,7 @@ void free_matrix(chebfd_matrix *H)
 
 // Builds SELL-C-sigma from a row generator.  rowfn(i, entries) fills row i.
 template <typename RowFn>
-int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn)
+int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool pair_rows)
 {
     Sell &S = H->sell;
     S.n = n;
@@ -136,6 +136,52 @@ int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn)
         std::iota(ids.begin(), ids.end(), (int32_t)w0);
         std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
         std::copy(ids.begin(), ids.end(), perm.begin() + w0);
+    }
+    // inside each chunk, place rows that gather the same columns at the same
+    // entry positions next to each other: slots 2k and 2k+1 share one wave
+    // instruction at 32 lanes per row, and equal addresses in one
+    // instruction are one cache access (greedy pairing by the number of
+    // positions with equal column index)
+    if (pair_rows) {
+        std::vector<std::vector<int64_t>> cols(C);
+        std::vector<Entry> er;
+        std::vector<int32_t> order;
+        std::vector<char> used;
+        for (int64_t c = 0; c < S.nchunks; ++c) {
+            int nv = 0;
+            for (int r = 0; r < C; ++r) {
+                const int32_t i = perm[c * C + r];
+                cols[r].clear();
+                if (i < 0) continue;
+                ++nv;
+                rowfn(i, er);
+                for (const Entry &e : er) cols[r].push_back(e.c);
+            }
+            if (nv < 3) continue;
+            order.clear();
+            used.assign(C, 0);
+            for (int r = 0; r < nv; ++r) {
+                if (used[r]) continue;
+                used[r] = 1;
+                order.push_back(perm[c * C + r]);
+                int best = -1, bo = -1;
+                for (int r2 = r + 1; r2 < nv; ++r2) {
+                    if (used[r2]) continue;
+                    const size_t m = std::min(cols[r].size(), cols[r2].size());
+                    int ov = 0;
+                    for (size_t j = 0; j < m; ++j) ov += cols[r][j] == cols[r2][j];
+                    if (ov > bo) {
+                        bo = ov;
+                        best = r2;
+                    }
+                }
+                if (best >= 0) {
+                    used[best] = 1;
+                    order.push_back(perm[c * C + best]);
+                }
+            }
+            std::copy(order.begin(), order.end(), perm.begin() + c * C);
+        }
     }
     std::vector<int64_t> cptr(S.nchunks + 1, 0);
     std::vector<int32_t> clen(S.nchunks, 0);
@@ -248,7 +294,7 @@ extern "C" int chebfd_matrix_from_csr(chebfd_ctx *ctx, int64_t n, const int64_t 
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
             r.push_back({(int64_t)col[p], cd(val[2 * p], val[2 * p + 1])});
     };
-    int rc = build_sell(H, n, sell_C, sell_sigma, rowfn);
+    int rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
     if (rc) {
         free_matrix(H);
         delete H;
@@ -290,7 +336,7 @@ extern "C" int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc
     };
     int rc = CHEBFD_OK;
     if (storage == CHEBFD_STORAGE_SELL) {
-        rc = build_sell(H, n, sell_C, sell_sigma, rowfn);
+        rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
         if (rc == CHEBFD_OK) rc = build_ti_schedule(H, L);
     } else {
         Stencil &S = H->st;

@@ -280,11 +280,11 @@ struct Solver {
             auto ta = clk::now();
             if (prec == CHEBFD_PREC_C64) {
                 rc = filter_apply(ctx, H, CHEBFD_PREC_C64, gamma.data(), p.n_p, a, b, X32, U32,
-                                  W32, k & 1 ? k + 1 : k, ns, nullptr);
+                                  W32, k & 1 ? k + 1 : k, ns, nullptr, p.verbose ? 1024 : 0);
                 ++st.iterations_c64;
             } else {
                 rc = filter_apply(ctx, H, CHEBFD_PREC_C128, gamma.data(), p.n_p, a, b, X, U, W, k,
-                                  ns, nullptr);
+                                  ns, nullptr, p.verbose ? 1024 : 0);
             }
             if (rc) return rc;
             st.n_mvm += (int64_t)k * p.n_p;
@@ -362,19 +362,29 @@ struct Solver {
                 // FP32 phase: switch to FP64 once the in-window residuals sit
                 // below polish_switch or stop improving
                 double mx = 0.0;
+                std::vector<double> good_r;
                 for (int j = 0; j < k; ++j)
-                    if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= seps)
+                    if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= seps) {
                         mx = std::max(mx, res[j]);
+                        good_r.push_back(res[j]);
+                    }
+                double med = INFINITY;
+                if (!good_r.empty()) {
+                    std::nth_element(good_r.begin(), good_r.begin() + good_r.size() / 2, good_r.end());
+                    med = good_r[good_r.size() / 2];
+                }
                 const int ngood = nconv + nconving;
                 // default threshold: a few FP32 roundings of the spectral scale
                 const double sw = std::max(std::fabs(a), std::fabs(b));
                 const double thr = std::isnan(p.polish_switch) ? 4.0 * 0x1p-23 * sw : p.polish_switch;
                 const bool below = ngood > 0 && mx <= thr;
-                // stalled: the set of good pairs did not grow and their worst
-                // residual no longer halves (the FP32 floor)
-                const bool stalled = it >= 2 && ngood > 0 && ngood <= prev_good &&
-                                     mx > 0.5 * prev_worst;
-                prev_worst = ngood > 0 ? mx : INFINITY;
+                // stalled: the set of good pairs grew by at most 5% and their
+                // median residual no longer halves (the FP32 floor; a few
+                // slow pairs are left to the FP64 polish)
+                const bool stalled = it >= 2 && ngood > 0 &&
+                                     ngood <= prev_good + std::max(1, prev_good / 20) &&
+                                     med > 0.5 * prev_worst;
+                prev_worst = ngood > 0 ? med : INFINITY;
                 prev_good = ngood;
                 if (below || stalled) {
                     prec = CHEBFD_PREC_C128;   // X (c128 Ritz vectors) continues in FP64

@@ -195,8 +195,8 @@ def test_launch_settings_give_identical_blocks(env, storage):
                 dict(xcd_group=8, order=1), dict(gathers=8), dict(pipeline=1),
                 dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
                 dict(order=2, pipeline=1, xcd_group=4), dict(batches=2),
-                dict(batches=2, lanes=64)]
-    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1)
+                dict(batches=2, lanes=64), dict(waves=4)]
+    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5)
     outs, moms = [], []
     try:
         for cfg in settings:
@@ -382,3 +382,25 @@ def test_solve_is_bitwise_reproducible(env):
     r2 = B.chebfd_solve(ctx, H, p)
     assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
     assert np.array_equal(r1[3], r2[3])
+
+
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
+def test_solve_empty_window(env, orc, storage):
+    """A window inside [a, b] that holds no eigenvalue: the exit rule ends
+    the run with no pair (the reference agrees: its dense spectrum has none
+    there, and its own solver returns none)."""
+    torch, B, ctx = env
+    L = (4, 4, 4)
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=1)
+    w = np.linalg.eigvalsh(Hr.dense())
+    lo, hi = w.max() + 0.5, w.max() + 1.0
+    a, b = orc.gershgorin(Hr)
+    assert hi < b and not np.any((w >= lo) & (w <= hi))
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1, storage=st)
+    p = B.default_params(lam_lo=lo, lam_hi=hi, n_s=16, n_p=60, eps=1e-9, seed=3, max_iter=20)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    assert rc == 0 and ev.size == 0, (rc, ev, stats)
+    assert stats["iterations"] < 20
+    st_o, ev_o, _, _, _ = orc.chebfd_solve(Hr, lo, hi, 16, 60, seed=3, max_iter=20)
+    assert st_o == 0 and ev_o.size == 0

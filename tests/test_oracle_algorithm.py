@@ -213,3 +213,14 @@ def test_golden_dense_spectra_vs_lapack(orc, seed):
     assert w.size == 2048
     assert np.abs(w - wl).max() < 1e-11
     assert np.abs(w[0::2] - w[1::2]).max() < 1e-11
+
+
+def test_solve_empty_window_returns_nothing(orc):
+    """A window that holds no eigenvalue (checked against LAPACK): the exit
+    rule of Sec. 3.1 step 8 ends the run with no pair and status 0."""
+    H = orc.ti_hamiltonian(4, 4, 4, pbc=3, V=1.0, seed=1)
+    w = np.linalg.eigvalsh(H.dense())
+    lo, hi = w.max() + 0.5, w.max() + 1.0
+    st, ev, rs, V, stats = orc.chebfd_solve(H, lo, hi, 16, 60, seed=3, max_iter=20)
+    assert st == 0 and ev.size == 0
+    assert stats["iterations"] < 20
