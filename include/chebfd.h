@@ -234,6 +234,9 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *   "pipeline"    SELL only: 0 (default) = one row block per workgroup,
  *                 1 = persistent workgroups that stage the next row block
  *                 while the current one is gathered;
+ *   "slab_group"  SELL only: column slabs taken G at a time with the G slabs
+ *                 of a row block back to back (one staging from memory per
+ *                 group); a power of two, 0 (default) = from "order";
  *   "pair_rows"   SELL matrices built on this context: 1 (default) = inside
  *                 each chunk, rows whose entries gather the same columns at
  *                 the same positions are placed in adjacent slots (one wave

@@ -355,6 +355,8 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     else if (k == "batches" && (value == 1 || value == 2)) ctx->tune_batches = value;
     else if (k == "waves" && (value == 4 || value == 5)) ctx->tune_waves = value;
     else if (k == "pair_rows" && (value == 0 || value == 1)) ctx->tune_pair_rows = value;
+    else if (k == "slab_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
+        ctx->tune_slab_group = value;
     else if (k == "xcd_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
         ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");

@@ -79,6 +79,7 @@ struct chebfd_ctx {
     int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
     int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
     int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
+    int tune_slab_group = 0; // SELL: slabs per group (0 = from order), a power of two
     int tune_pair_rows = 1; // SELL build: pair rows with equal gather columns in a chunk
     int tune_waves = 5;     // SELL: occupancy target of the staged kernel (waves per SIMD), 4 or 5
     int tune_batches = 1;   // stencil: neighbour loads in 1 batch or 2 (in-plane, then z)

@@ -161,10 +161,13 @@ struct BlockLoc {
     int64_t base;
 };
 
-// Logical work item l -> block.  order 0: slab-major (all row blocks of a
-// column slab, then the next slab); order 1: block-major.  The row blocks
-// per chunk are a power of two (2^lg_bpc).  With a schedule, the row blocks
-// visit the chunks in the scheduled order.
+// Logical work item l -> block.  `order` is the slab-group size G: the
+// column slabs are taken G at a time, and inside a group the G slabs of a
+// row block run back to back (G = 1: slab-major, G = nslab: block-major), so
+// a row block's index stream is staged from memory once per group and from
+// L2 for the other slabs of the group.  The row blocks per chunk are a
+// power of two (2^lg_bpc).  With a schedule, the row blocks visit the chunks
+// in the scheduled order.
 __device__ __forceinline__ BlockLoc locate(uint32_t l, int order, uint32_t nrb, uint32_t nslab,
                                           int C, int lg_bpc, int RB,
                                           const int64_t *__restrict__ chunk_ptr,
@@ -172,13 +175,15 @@ __device__ __forceinline__ BlockLoc locate(uint32_t l, int order, uint32_t nrb, 
                                           const int32_t *__restrict__ sched)
 {
     BlockLoc L;
-    if (order == 0) {
-        L.slab = l / nrb;
-        L.rb = l - L.slab * nrb;
-    } else {
-        L.rb = l / nslab;
-        L.slab = l - L.rb * nslab;
-    }
+    // slab groups of G = order slabs: all row blocks of a group, each with
+    // the group's slabs adjacent (G = 1: slab-major, G = nslab: block-major)
+    const uint32_t G = (uint32_t)order;
+    const uint32_t per = nrb * G;
+    const uint32_t sg = l / per;
+    const uint32_t g = (nslab - sg * G) < G ? (nslab - sg * G) : G;
+    const uint32_t rem = l - sg * per;
+    L.rb = rem / g;
+    L.slab = sg * G + (rem - L.rb * g);
     L.chunk = sched ? (uint32_t)sched[L.rb >> lg_bpc] : L.rb >> lg_bpc;
     L.r0 = (L.rb & ((1u << lg_bpc) - 1)) * RB;
     L.len = chunk_len[L.chunk];
@@ -540,12 +545,16 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
         return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
     g.RB = S.C < RPP ? S.C : RPP;
     g.lg_bpc = ilog2(S.C / g.RB);
-    // order 2 follows the matrix's chunk schedule (if it has one) slab-major
-    g.order = ctx->tune_order == 1 ? 1 : 0;
+    // slab-group size (order 1: block-major; order 2 follows the matrix's
+    // chunk schedule, if it has one, slab-major)
+    int G = ctx->tune_order == 1 ? (int)nslab : 1;
+    if (ctx->tune_slab_group > 0) G = (int)std::min<int64_t>(ctx->tune_slab_group, nslab);
+    g.order = G;
     g.sched = ctx->tune_order == 2 ? S.sched : nullptr;
-    // default placement: the row blocks of one chunk share an XCD; under a
-    // schedule, one locality group of chunks does
+    // default placement: the row blocks of one chunk (and the slabs of a
+    // group) share an XCD; under a schedule, one locality group of chunks does
     int grp = S.C / g.RB;
+    if (G > 1) grp *= G;
     if (g.sched && S.sched_group > 0) grp *= S.sched_group;
     g.lg_xg = ilog2(ctx->tune_xcd_group ? ctx->tune_xcd_group : grp);
     g.nrb = (uint32_t)nrb;

@@ -195,8 +195,10 @@ def test_launch_settings_give_identical_blocks(env, storage):
                 dict(xcd_group=8, order=1), dict(gathers=8), dict(pipeline=1),
                 dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
                 dict(order=2, pipeline=1, xcd_group=4), dict(batches=2),
-                dict(batches=2, lanes=64), dict(waves=4)]
-    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5)
+                dict(batches=2, lanes=64), dict(waves=4), dict(slab_group=2),
+                dict(slab_group=4, lanes=16), dict(slab_group=2, pipeline=1)]
+    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5,
+                    slab_group=0)
     outs, moms = [], []
     try:
         for cfg in settings:
