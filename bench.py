@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the bandwidth probe and the timed fused launches")
+    ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
+                    help="spectral interval for the scaling: Gershgorin (default) or 40 "
+                         "Lanczos steps, checked by the solver")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-storage", action="store_true",
                     help="skip the fused-kernel timing (and solve) of the other storage")
@@ -166,6 +169,11 @@ def main():
     info = H.info()
     n, nnz = info["n"], info["nnz"]
     a, b = info["g_lo"], info["g_hi"]
+    lanczos_steps = 0
+    if args.bounds == "lanczos":
+        # the same estimate the solver makes (same seed and steps)
+        lanczos_steps = 40
+        a, b = B.chebfd_lanczos_bounds(ctx, H, k=lanczos_steps, seed=w["seeds"][0])
     mat_bytes = info["matrix_bytes_c128"] if prec == B.PREC_C128 else info["matrix_bytes_c64"]
     vb = mat_bytes + 5 * n * n_s * s_d              # algorithmic bytes per fused launch
     print(f"# matrix {args.storage} N={n} nnz={nnz} built in {t_build:.2f} s", flush=True)
@@ -196,7 +204,7 @@ def main():
     }
     cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "n_s": n_s,
            "n_p": n_p, "eta": round(eta, 2), "kernel": w["kernel"], "window": [-delta, delta],
-           "storage": args.storage,
+           "storage": args.storage, "bounds": [round(a, 4), round(b, 4), args.bounds],
            "sell_C_sigma": [w.get("sell_C"), w.get("sell_sigma")] if args.storage == "sell" else None,
            "eps": w["eps"]}
 
@@ -207,7 +215,8 @@ def main():
     else:
         params = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p,
                                   kernel=w["kernel"], mu=w["mu"], eps=w["eps"], max_iter=60,
-                                  precision=prec, lock=1, seed=w["seeds"][0], vectors=0)
+                                  precision=prec, lock=1, seed=w["seeds"][0], vectors=0,
+                                  bounds=lanczos_steps)
         for _ in range(args.warmup):
             B.chebfd_solve(ctx, H, params)
         torch.cuda.synchronize()

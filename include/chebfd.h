@@ -255,6 +255,18 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  * Errors: INVALID_ARG for an unknown key or value. */
 int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value);
 
+/* Spectral interval [a, b] of H from k steps of the Lanczos process, the
+ * alternative to the Gershgorin bound for the scaling of Sec. 3.1 step 1.
+ * Random start vector (stream 4 of `seed`), no reorthogonalisation; the
+ * extreme Ritz values are widened by their residual bounds beta_k |s_k| and
+ * by `pad` times the Ritz range, and clamped to the Gershgorin interval.
+ * Not a rigorous enclosure: chebfd_solve checks its Rayleigh quotients
+ * against the interval and falls back to Gershgorin if one lies outside.
+ * Allocates 3 N complex128 of device memory for the call.  Synchronises.
+ * Errors: INVALID_ARG (k outside [2, 1000], pad < 0), NONFINITE. */
+int chebfd_lanczos_bounds(chebfd_ctx *ctx, const chebfd_matrix *H, int k, uint64_t seed,
+                          double pad, double *a, double *b);
+
 /* Attainable HBM bandwidth: gbs[0] the read-only reduction benchmark of
  * Sec. 4.1, gbs[1] a plain copy (bytes read + written), gbs[2] the fused
  * step's streams without the gather (read three blocks, write two:
@@ -379,6 +391,11 @@ typedef struct {
     int vectors;             /* 1: copy the eigenvectors to the host result */
     int verbose;             /* 1: progress on stderr: one line per outer
                                 iteration and per 1024 filter steps */
+    int bounds;              /* with a = b = NaN: 0 Gershgorin interval, k > 0
+                                Lanczos bounds with k steps (pad 0.01, start
+                                vector from `seed`), checked against every
+                                Rayleigh quotient with a fallback to
+                                Gershgorin */
 } chebfd_params;
 
 typedef struct {
@@ -395,7 +412,7 @@ typedef struct {
 
 /* Fills `p` with defaults: Lanczos kernel mu = 2, eps 1e-9, max_iter 50, C128,
  * lock 1, a = b = NaN, seed 1, polish_switch NaN, vectors 1, verbose 0,
- * n_s 32, n_p 200. */
+ * bounds 0, n_s 32, n_p 200. */
 int chebfd_params_default(chebfd_params *p);
 
 /* Device workspace (bytes) chebfd_solve needs for this matrix and params. */

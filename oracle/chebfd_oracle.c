@@ -592,8 +592,10 @@ void orc_rayleigh_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, con
 /*  - exit (step 8) once, after at least two iterations, no in-window pair  */
 /*    is converging, the converged count equals that of the previous        */
 /*    iteration, and the smallest residual among the remaining in-window    */
-/*    pairs fell by less than 10% (those pairs are ghosts: a large residual */
-/*    that does not decrease; a slowly converging pair still gains more);   */
+/*    pairs fell by less than 10% while none has converged, or by less     */
+/*    than half once some have (those pairs are ghosts: a large residual    */
+/*    that does not decrease; before the first convergence a slowly         */
+/*    converging search space still gains more than 10% per iteration);     */
 /*  - the restart block is the full set of n_s Ritz vectors (step 8b).      */
 /* Outputs the converged in-window pairs in ascending order.                 */
 /* ------------------------------------------------------------------------ */
@@ -642,7 +644,7 @@ int orc_chebfd_solve(int64_t n, const int64_t *rowptr, const int32_t *col, const
                 if (res[k] < rmin) rmin = res[k];
             }
         }
-        int stagnant = (rmin == INFINITY) || (rmin >= 0.9 * prev_rmin);
+        int stagnant = (rmin == INFINITY) || (rmin >= (nconv > 0 ? 0.5 : 0.9) * prev_rmin);
         if (it >= 2 && nconving == 0 && nconv == prev_conv && stagnant) { status = 0; break; }
         prev_conv = nconv;
         prev_rmin = rmin;

@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("max_iter", C.c_int), ("precision", C.c_int), ("lock", C.c_int),
                 ("a", C.c_double), ("b", C.c_double), ("seed", C.c_uint64),
                 ("gamma_corr", C.c_void_p), ("polish_switch", C.c_double), ("vectors", C.c_int),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("bounds", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -76,6 +76,7 @@ def lib():
         "chebfd_filter_quality": (i32, [vp, i32, dbl, dbl, dbl, dbl, dbl, dbl, vp, vp]),
         "chebfd_optimal_np": (i32, [dbl, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "chebfd_filter_apply": (i32, [vp, vp, i32, vp, i32, dbl, dbl, vp, vp, vp, i64, i64, vp]),
+        "chebfd_lanczos_bounds": (i32, [vp, vp, i32, u64, dbl, vp, vp]),
         "chebfd_spmm": (i32, [vp, vp, i32, vp, vp, i64, i64, dbl, dbl]),
         "chebfd_gram": (i32, [vp, i32, vp, i64, i64, vp, i64, i64, i64, vp]),
         "chebfd_block_times": (i32, [vp, i32, vp, i64, i64, i64, vp, i64, i32, vp, i64, i32]),
@@ -121,6 +122,7 @@ def exported_symbols():
                         "chebfd_last_error chebfd_version chebfd_matrix_from_csr chebfd_matrix_ti "
                         "chebfd_matrix_info chebfd_matrix_destroy chebfd_coeffs "
                         "chebfd_filter_quality chebfd_optimal_np chebfd_filter_apply chebfd_spmm "
+                        "chebfd_lanczos_bounds "
                         "chebfd_gram chebfd_block_times chebfd_residual_norms "
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
                         "chebfd_params_default chebfd_solve_workspace_size chebfd_solve "
@@ -316,6 +318,14 @@ def chebfd_random_block(ctx, X, seed, stream=1, offset=0, k0=0, m=None):
 def chebfd_convert(ctx, X, Y):
     _check(lib().chebfd_convert(ctx.h, _prec(X), _ptr(X), _prec(Y), _ptr(Y), X.shape[0],
                                 X.shape[1], _ld(X), _ld(Y)))
+
+
+def chebfd_lanczos_bounds(ctx, H, k=40, seed=1, pad=0.01):
+    """(a, b) from k Lanczos steps (see include/chebfd.h)."""
+    a, b = C.c_double(), C.c_double()
+    _check(lib().chebfd_lanczos_bounds(ctx.h, H.h, int(k), int(seed), float(pad), C.byref(a),
+                                       C.byref(b)))
+    return a.value, b.value
 
 
 def chebfd_set_tuning(ctx, key, value):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchebfd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.cpp", "matrix.cpp", "host_poly.cpp", "host_eig.cpp", "solver.cpp", "learned.cpp",
+SOURCES = ["capi.cpp", "matrix.cpp", "host_poly.cpp", "host_eig.cpp", "solver.cpp", "learned.cpp", "lanczos.cpp",
            "kernels_step.hip", "kernels_stencil.hip", "kernels_dense.hip", "kernels_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

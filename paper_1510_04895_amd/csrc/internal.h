@@ -151,6 +151,10 @@ int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double
                  double *mom, int progress = 0);
 int check_block(const char *who, int precision, const void *p, int64_t n, int64_t n_s,
                 int64_t ld, bool packed);
+// Lanczos spectral bounds (lanczos.cpp); V3 = n x 3 c128 scratch (ld 3),
+// S_dev 2 doubles, T_dev 4 doubles of device scratch.
+int lanczos_bounds(chebfd_ctx *ctx, const chebfd_matrix *H, int k, uint64_t seed, double pad,
+                   void *V3, double *S_dev, double *T_dev, double *a_out, double *b_out);
 
 // ---------------------------------------------------------------- host math
 void window_coeffs(double lo, double hi, double a, double b, int n_p, double *c);

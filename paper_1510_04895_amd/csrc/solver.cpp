@@ -13,8 +13,9 @@
 //    eps < r <= sqrt(eps), a ghost candidate otherwise;
 //  - exit after >= 2 iterations once no in-window pair is converging, the
 //    converged count has not changed, and the smallest remaining in-window
-//    residual fell by less than 10% (ghosts: a large residual that does
-//    not decrease; a slowly converging pair still gains more);
+//    residual fell by less than 10% while nothing has converged, or by less
+//    than half once some pairs have (ghosts: a large residual that does not
+//    decrease; a slowly converging search space gains more);
 //  - the restart block is the set of Ritz vectors.
 // Locking (a refinement the paper lists in Sec. 6): converged in-window
 // pairs move to a locked set Q, later blocks are kept orthogonal to Q and
@@ -105,6 +106,8 @@ struct Solver {
     double a = 0, b = 0;
     chebfd_stats st{};
     uint64_t refill_ctr = 0;
+    bool bounds_checked = false;   // [a, b] is an estimate: verify every Rayleigh quotient
+    static constexpr int RESTART_WIDER = 1000;
 
     int sync() { CHEBFD_HIP(hipStreamSynchronize(ctx->stream)); return CHEBFD_OK; }
 
@@ -325,6 +328,16 @@ struct Solver {
             if ((rc = launch_residuals(ctx, CHEBFD_PREC_C128, W, X, n, k, ns, dTheta, dRes))) return rc;
             res.resize(k);
             if ((rc = down(res.data(), dRes, (size_t)k * 8))) return rc;
+            if (bounds_checked) {
+                // a Rayleigh quotient lies in the convex hull of the
+                // spectrum: one outside [a, b] (or an overflow of the filter)
+                // proves the estimated interval too narrow
+                const double tol = 1e-10 * std::max(std::fabs(a), std::fabs(b));
+                for (int j = 0; j < k; ++j)
+                    if (!std::isfinite(theta[j]) || !std::isfinite(res[j]) || theta[j] < a - tol ||
+                        theta[j] > b + tol)
+                        return RESTART_WIDER;
+            }
             for (int j = 0; j < k; ++j)
                 if (!std::isfinite(theta[j]) || !std::isfinite(res[j]))
                     return fail(CHEBFD_ERR_NONFINITE, "non-finite Ritz pair");
@@ -460,7 +473,8 @@ struct Solver {
                 }
             }
             const int total_conv = p.lock ? n_lock : nconv;
-            const bool stagnant = (rmin == INFINITY) || (rmin >= 0.9 * prev_rmin);
+            const bool stagnant =
+                (rmin == INFINITY) || (rmin >= (total_conv > 0 ? 0.5 : 0.9) * prev_rmin);
             if (it >= 2 && nconving == 0 && total_conv == prev_conv && stagnant) {
                 status = CHEBFD_OK;
                 break;
@@ -586,6 +600,8 @@ static int check_params(const chebfd_matrix *H, const chebfd_params *p)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: unknown precision");
     if (p->precision == CHEBFD_PREC_C64 && (p->n_s & 1))
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: the c64 form needs an even n_s");
+    if (p->bounds < 0 || p->bounds == 1 || p->bounds > 1000)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: bounds must be 0 (Gershgorin) or 2..1000 Lanczos steps");
     return CHEBFD_OK;
 }
 
@@ -616,23 +632,60 @@ extern "C" int chebfd_solve(chebfd_ctx *ctx, const chebfd_matrix *H, const chebf
     if (!workspace || workspace_bytes < (int64_t)S.L.total || ((uintptr_t)workspace & 255))
         return fail(CHEBFD_ERR_WORKSPACE, "chebfd_solve: workspace missing, too small or not 256-byte aligned");
     S.ws = (char *)workspace;
+    CHEBFD_HIP(hipSetDevice(ctx->device));
     S.a = std::isnan(p->a) ? H->g_lo : p->a;
     S.b = std::isnan(p->b) ? H->g_hi : p->b;
+    if (std::isnan(p->a) && std::isnan(p->b) && p->bounds > 0 && p->n_s >= 3) {
+        // Lanczos bounds, computed in the (still unused) workspace: the
+        // first block as the three Lanczos vectors, the small area as scratch
+        char *base = (char *)workspace;
+        double lo, hi;
+        if ((rc = lanczos_bounds(ctx, H, p->bounds, p->seed, 0.01, base + S.L.off_b[0],
+                                 (double *)(base + S.L.off_small),
+                                 (double *)(base + S.L.off_small + 256), &lo, &hi)))
+            return rc;
+        if (lo < hi && p->lam_lo > lo && p->lam_hi < hi) {
+            S.a = lo;
+            S.b = hi;
+            S.bounds_checked = true;
+        }
+    }
     if (!(S.a < S.b)) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: empty spectral interval");
     if (p->lam_hi <= S.a || p->lam_lo >= S.b)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: window outside the spectral interval");
-    S.gamma.resize(p->n_p + 1);
-    if ((rc = chebfd_coeffs(p->lam_lo, p->lam_hi, S.a, S.b, p->n_p, p->kernel, p->mu, S.gamma.data())))
-        return rc;
-    if (p->gamma_corr)
-        for (int k = 0; k <= p->n_p; ++k) {
-            if (!std::isfinite(p->gamma_corr[k]))
-                return fail(CHEBFD_ERR_NONFINITE, "chebfd_solve: non-finite coefficient correction");
-            S.gamma[k] *= 1.0 + p->gamma_corr[k];
-        }
-    CHEBFD_HIP(hipSetDevice(ctx->device));
+    auto coeffs = [&]() -> int {
+        S.gamma.assign(p->n_p + 1, 0.0);
+        int r = chebfd_coeffs(p->lam_lo, p->lam_hi, S.a, S.b, p->n_p, p->kernel, p->mu,
+                              S.gamma.data());
+        if (r) return r;
+        if (p->gamma_corr)
+            for (int k = 0; k <= p->n_p; ++k) {
+                if (!std::isfinite(p->gamma_corr[k]))
+                    return fail(CHEBFD_ERR_NONFINITE, "chebfd_solve: non-finite coefficient correction");
+                S.gamma[k] *= 1.0 + p->gamma_corr[k];
+            }
+        return CHEBFD_OK;
+    };
+    if ((rc = coeffs())) return rc;
     auto *res = new chebfd_result();
     rc = S.run(res);
+    if (rc == Solver::RESTART_WIDER) {
+        // the estimated interval was too narrow: start again on Gershgorin's
+        const chebfd_stats first = S.st;
+        S.a = H->g_lo;
+        S.b = H->g_hi;
+        S.bounds_checked = false;
+        S.st = chebfd_stats{};
+        S.refill_ctr = 0;
+        if ((rc = coeffs())) {
+            delete res;
+            return rc;
+        }
+        *res = chebfd_result();
+        rc = S.run(res);
+        res->stats.iterations += first.iterations;
+        res->stats.n_mvm += first.n_mvm;
+    }
     if (rc < 0) {
         delete res;
         return rc;

@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--storage", default="stencil", choices=["sell", "stencil"])
     ap.add_argument("--forms", default="fp64,c64,c64_learned")
     ap.add_argument("--max-iter", type=int, default=40)
+    ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
+                    help="spectral interval: Gershgorin or 40 Lanczos steps (checked by the solver)")
     ap.add_argument("--plan-only", action="store_true",
                     help="only the window, the rule's N_p and the fused-step time per precision")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_1510_04895_amd", "models",
@@ -74,6 +76,10 @@ def main():
     H = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st)
     info = H.info()
     n, a, b = info["n"], info["g_lo"], info["g_hi"]
+    lanczos_steps = 0
+    if args.bounds == "lanczos":
+        lanczos_steps = 40
+        a, b = B.chebfd_lanczos_bounds(ctx, H, k=lanczos_steps, seed=w["seeds"][0])
     mu_c = B.chebfd_kpm_moments(ctx, H, learned.N_VEC, N_MOM_COUNT, w["seeds"][0], a, b,
                                 precision=B.PREC_C64)
     mu = mu_c[:learned.N_MOM]
@@ -84,7 +90,8 @@ def main():
     # small margins of N_S/N_T near 1
     _, _, np_rule, margin = B.chebfd_dos_params(mu_c, n, a, b, -delta, delta, n_s=n_s,
                                                  ns_max=n_s, with_margin=True)
-    print(json.dumps(dict(workload=args.workload, N=n, a=a, b=b, delta=delta, nt_est=nt,
+    print(json.dumps(dict(workload=args.workload, N=n, a=a, b=b, bounds=args.bounds, delta=delta,
+                          nt_est=nt,
                           np_rule=np_rule, margin=margin,
                           setup_s=round(time.perf_counter() - t0, 2))), flush=True)
     if args.plan_only:
@@ -122,7 +129,8 @@ def main():
             n_p, _, corr = learned.predict(ctx, net, P, n_s_fixed=n_s)
         torch.cuda.synchronize()
         r = learned.run_solve(ctx, H, delta, n_s, n_p, corr=corr, precision=prec,
-                              max_iter=args.max_iter, seed=w["seeds"][0], verbose=1)
+                              max_iter=args.max_iter, seed=w["seeds"][0], verbose=1,
+                              bounds=lanczos_steps)
         row = dict(form=form, n_p=n_p, corrections=corr is not None, status=r["rc"],
                    found=r["found"], time_s=r["time"],
                    n_mvm=r["n_mvm"], iterations=r["iterations"],

@@ -6,6 +6,7 @@ polynomial of degree n_p in a matrix of norm <= 1 after scaling, so rounding
 grows at most linearly in n_p; FP32 paths sqrt(n_p) * 2^-24 * 30 relative.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -406,3 +407,49 @@ def test_solve_empty_window(env, orc, storage):
     assert stats["iterations"] < 20
     st_o, ev_o, _, _, _ = orc.chebfd_solve(Hr, lo, hi, 16, 60, seed=3, max_iter=20)
     assert st_o == 0 and ev_o.size == 0
+
+
+# ------------------------------------------------------------ Lanczos bounds
+@pytest.mark.parametrize("case", ["ti444", "ti654", "csr"])
+def test_lanczos_bounds_enclose_spectrum(env, orc, case):
+    """Lanczos bounds (Sec. 3.1 step 1) contain the whole spectrum (LAPACK on
+    the dense matrix) and lie inside the Gershgorin interval."""
+    torch, B, ctx = env
+    if case == "csr":
+        rp, col, val = inp.random_hermitian_csr(997, seed=5, min_row=2, max_row=20)
+        Hr = orc.CSR(997, rp, col, val)
+        H = B.Matrix.from_csr(ctx, rp, col, val)
+    else:
+        L = (4, 4, 4) if case == "ti444" else (6, 5, 4)
+        Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=7)
+        H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=7)
+    w = np.linalg.eigvalsh(Hr.dense())
+    ga, gb = orc.gershgorin(Hr)
+    a, b = B.chebfd_lanczos_bounds(ctx, H, k=40, seed=3)
+    assert ga <= a <= w.min() and w.max() <= b <= gb, (a, b, w.min(), w.max(), ga, gb)
+
+
+@pytest.mark.parametrize("steps", [40, 2])
+def test_solve_with_lanczos_bounds(env, orc, steps):
+    """The solve on Lanczos bounds finds the dense oracle's eigenvalues; with
+    2 steps the estimate may be too narrow, which the solver must detect
+    from its Rayleigh quotients and recover from on the Gershgorin
+    interval."""
+    torch, B, ctx = env
+    L = (8, 8, 8)
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                   "ti_8x8x8_V1_seed1_evals.txt"))
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1)
+    aw = np.sort(np.abs(gold))
+    d = 0.5 * (aw[15] + aw[16])
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=200, eps=1e-9, seed=1, bounds=steps)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    want = np.sort(gold[np.abs(gold) <= d])
+    info = H.info()
+    S_w = max(abs(info["g_lo"]), abs(info["g_hi"]))
+    assert rc == 0 and ev.size == want.size == 16, (rc, ev, stats)
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    assert info["g_lo"] <= stats["a"] < gold.min() and gold.max() < stats["b"] <= info["g_hi"]
+    if steps == 40:
+        assert stats["b"] - stats["a"] < 0.8 * (info["g_hi"] - info["g_lo"])
