@@ -389,13 +389,13 @@ struct Solver {
                 const int ngood = nconv + nconving;
                 // default threshold: a few FP32 roundings of the spectral scale
                 const double sw = std::max(std::fabs(a), std::fabs(b));
-                const double thr = std::isnan(p.polish_switch) ? 4.0 * 0x1p-23 * sw : p.polish_switch;
+                const double thr = std::isnan(p.polish_switch) ? 8.0 * 0x1p-23 * sw : p.polish_switch;
                 const bool below = ngood > 0 && mx <= thr;
-                // stalled: the set of good pairs grew by at most 5% and their
+                // stalled: the set of good pairs grew by at most 10% and their
                 // median residual no longer halves (the FP32 floor; a few
                 // slow pairs are left to the FP64 polish)
                 const bool stalled = it >= 2 && ngood > 0 &&
-                                     ngood <= prev_good + std::max(1, prev_good / 20) &&
+                                     ngood <= prev_good + std::max(1, prev_good / 10) &&
                                      med > 0.5 * prev_worst;
                 prev_worst = ngood > 0 ? med : INFINITY;
                 prev_good = ngood;
