@@ -71,3 +71,20 @@ def test_step_flops_paper_convention():
     F_a, F_m = 2, 6
     per = 13 * (F_a + F_m) + -(-9 * F_a // 2) + -(-11 * F_m // 2)
     assert bench.step_flops(10, 3, 13) == 10 * 3 * per
+
+
+def test_kpm_window_count_on_the_chebyshev_density():
+    """mu_m = delta_{m0} is the density 1/(pi sqrt(1 - x^2)) on [-1, 1]; the
+    count of Eq. DOS:target in [-d, d] is N (2/pi) asin(d), and the window
+    search inverts it."""
+    import math
+    import numpy as np
+    from paper_1510_04895_amd import scale_runs as sr
+    mu = np.zeros(4096)
+    mu[0] = 1.0
+    n = 1_000_000
+    for d in (0.05, 0.2, 0.6):
+        want = n * 2.0 / math.pi * math.asin(d)
+        assert sr.kpm_count(mu, n, -1.0, 1.0, d) == pytest.approx(want, rel=2e-3)
+    d = sr.window_for_count(mu, n, -1.0, 1.0, 100000)
+    assert n * 2.0 / math.pi * math.asin(d) == pytest.approx(100000, rel=2e-3)
