@@ -107,3 +107,30 @@ def test_mlp_training_reduces_loss(env):
     for _ in range(400):
         last = mlp.train_step(Xd, Td, lr=3e-3)
     assert last < 0.05 * first
+
+
+@pytest.mark.parametrize("seed", [10001, 10017])
+def test_trained_model_on_heldout_realisation(env, seed):
+    """The committed network on a held-out 32x32x16 realisation (seeds of
+    the evaluation set, never trained on): its (N_p, N_S, corrections),
+    gated by the damping-factor check, reach the same eigenvalues as the
+    DOS rule's parameters at residual <= 1e-9.  The work bound is a sanity
+    guard against a broken network or decoding (the held-out evaluation
+    saw ratios of matrix-vector products between 0.70 and 1.76 per
+    realisation), not a performance claim."""
+    import os
+    torch, B, ctx = env
+    from paper_1510_04895_amd import learned
+    path = os.path.join(os.path.dirname(learned.__file__), "models", "ti_32x32x16_mlp.npz")
+    net = learned.load_model(ctx, path)
+    P = learned.problem(ctx, seed)
+    base = learned.run_solve(ctx, P["H"], P["delta"], P["ns0"], P["np0"], seed=seed)
+    n_p, n_s, corr = learned.predict(ctx, net, P)
+    lrn = learned.run_solve(ctx, P["H"], P["delta"], n_s, n_p, corr=corr, seed=seed)
+    S_w = max(abs(P["a"]), abs(P["b"]))
+    assert base["rc"] == 0 and lrn["rc"] == 0
+    assert lrn["found"] == base["found"]
+    if base["found"]:
+        assert np.abs(lrn["evals"] - base["evals"]).max() < 1e-10 * S_w
+        assert lrn["res"].max() <= 1e-9
+    assert lrn["n_mvm"] <= 2.0 * base["n_mvm"]
