@@ -137,6 +137,9 @@ def main():
                     help="skip the extra solve on Lanczos bounds")
     ap.add_argument("--no-other-storage", action="store_true",
                     help="skip the fused-kernel timing (and solve) of the other storage")
+    ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="block order of the fused step (tuning key 'order'): -1 automatic, "
+                         "0 column-slab major, 1 row-chunk major, 2 lattice z-march")
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="fused launches timed with HIP events for the roofline figure")
     args = ap.parse_args()
@@ -152,6 +155,8 @@ def main():
     L = w["L"]
     n_s = w["n_s"]
     ctx = B.Context(0)
+    if args.order != -1:
+        B.chebfd_set_tuning(ctx, "order", args.order)
     stream = torch.cuda.current_stream()
     prec = B.PREC_C128 if args.precision == "c128" else B.PREC_C64
     s_d = 16 if prec == B.PREC_C128 else 8
@@ -182,9 +187,18 @@ def main():
 
     # window and filter degree (linear DOS near the centre: delta'/delta =
     # sqrt(N_S/N_T) - 1, Sec. 2.4; eta-minimising N_p, Sec. 2.3)
-    delta = w["delta"]
-    dp = delta * (math.sqrt(n_s / w["n_target"]) - 1.0)
-    n_p, eta = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
+    delta = w.get("delta")
+    if delta is not None:
+        dp = delta * (math.sqrt(n_s / w["n_target"]) - 1.0)
+        n_p, eta = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
+    elif args.kernel_only:
+        # the larger lattices take their window from the KPM count (their
+        # solves run through paper_1510_04895_amd.scale_runs); the timed
+        # launches need coefficients only
+        delta, n_p, eta = 0.02 * max(abs(a), abs(b)), None, None
+    else:
+        sys.exit(f"bench.py: {args.workload} has no fixed window; solve it with "
+                 "python -m paper_1510_04895_amd.scale_runs, or time its kernel with --kernel-only")
 
     # --- the fused kernel alone, timed with HIP events on the library stream
     ks = args.kernel_steps
@@ -205,7 +219,8 @@ def main():
         "data": "synthetic",
     }
     cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "n_s": n_s,
-           "n_p": n_p, "eta": round(eta, 2), "kernel": w["kernel"], "window": [-delta, delta],
+           "n_p": n_p, "eta": None if eta is None else round(eta, 2), "kernel": w["kernel"],
+           "window": [-delta, delta], "order": args.order,
            "storage": args.storage, "bounds": [round(a, 4), round(b, 4), args.bounds],
            "sell_C_sigma": [w.get("sell_C"), w.get("sell_sigma")] if args.storage == "sell" else None,
            "eps": w["eps"]}

@@ -226,7 +226,13 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *   "lanes"       lanes sharing one row (SELL) or site (stencil): 16, 32, 64,
  *                 0 = default (32; 16 for blocks of at most 16 packs);
  *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
- *   "order"       0 (default) = workgroups ordered column-slab major,
+ *   "order"       -1 (default) = automatic: the matrix-free lattice runs
+ *                 the z-march when, column-slab major, the bytes moved
+ *                 between a site's gather as a z-neighbour from above and
+ *                 from below (two lattice planes of the five block streams
+ *                 over one slab) exceed the 256 MB memory-side cache, and
+ *                 is column-slab major otherwise; SELL is column-slab major;
+ *                 0 = workgroups ordered column-slab major,
  *                 1 = row-chunk major, 2 = lattice z-march (matrices from
  *                 chebfd_matrix_ti: blocks of one z-column run consecutively
  *                 on one XCD; other matrices fall back to 0);

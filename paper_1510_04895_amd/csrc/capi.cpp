@@ -349,7 +349,7 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     const std::string k(key);
     if (k == "lanes" && (value == 0 || value == 16 || value == 32 || value == 64)) ctx->tune_lpr = value;
     else if (k == "nontemporal" && (value == 0 || value == 1)) ctx->tune_nt = value;
-    else if (k == "order" && value >= 0 && value <= 2) ctx->tune_order = value;
+    else if (k == "order" && value >= -1 && value <= 2) ctx->tune_order = value;
     else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
     else if (k == "pipeline" && (value == 0 || value == 1)) ctx->tune_pipeline = value;
     else if (k == "batches" && (value == 1 || value == 2)) ctx->tune_batches = value;

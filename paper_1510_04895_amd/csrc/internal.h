@@ -76,7 +76,7 @@ struct chebfd_ctx {
     // launch configuration of the fused step (chebfd_set_tuning)
     int tune_lpr = 0;     // lanes per row/site: 0 = default (32), 16, 32, 64
     int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
-    int tune_order = 0;   // 0 slab-major, 1 chunk-major workgroup order
+    int tune_order = -1;  // -1 automatic, 0 slab-major, 1 chunk-major, 2 lattice z-march
     int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
     int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
     int tune_slab_group = 0; // SELL: slabs per group (0 = from order), a power of two

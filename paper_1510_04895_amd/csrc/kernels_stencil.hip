@@ -304,13 +304,29 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
     }
 }
 
+// Default block order.  Column-slab major, a site is gathered as the
+// z-neighbour of the plane above and, two planes of work later, of the plane
+// below; in between the step moves two planes of its five block streams over
+// one slab.  Once that exceeds the memory-side cache (256 MB on MI355X) the
+// second gather goes back to HBM, and the z-march, which runs the planes of
+// one z-column back to back, wins (measured: 10-12% at 128x128x64 and
+// 256x256x64 with 256/128 columns, a loss at 64x64x32).
+template <typename T, int SW>
+int auto_order(const Stencil &S, int64_t n_s)
+{
+    constexpr double kMallBytes = 256.0 * (1 << 20);
+    const double slab_row = (double)(n_s < SW ? n_s : SW) * 2 * sizeof(T);
+    const double between = 2.0 * S.L[0] * S.L[1] * 4 * 5 * slab_row;
+    return between > kMallBytes ? 2 : 0;
+}
+
 template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
 int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
 {
     constexpr int SPB = 4 * (64 / LPS);
     constexpr int SW = LPS * NB;
     const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
-    const int order = ctx->tune_order;
+    const int order = ctx->tune_order >= 0 ? ctx->tune_order : auto_order<T, SW>(S, a.n_s);
     // z-march blocks cover whole x-runs of SPB sites (the last one ragged)
     const int64_t nblk = order == 2 ? (S.L[0] + SPB - 1) / SPB * S.L[1] * S.L[2]
                                     : (nsites + SPB - 1) / SPB;

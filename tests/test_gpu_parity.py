@@ -197,8 +197,8 @@ def test_launch_settings_give_identical_blocks(env, storage):
                 dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
                 dict(order=2, pipeline=1, xcd_group=4), dict(batches=2),
                 dict(batches=2, lanes=64), dict(waves=4), dict(slab_group=2),
-                dict(slab_group=4, lanes=16), dict(slab_group=2, pipeline=1)]
-    defaults = dict(lanes=0, order=0, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5,
+                dict(slab_group=4, lanes=16), dict(slab_group=2, pipeline=1), dict(order=0)]
+    defaults = dict(lanes=0, order=-1, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5,
                     slab_group=0)
     outs, moms = [], []
     try:
@@ -218,6 +218,36 @@ def test_launch_settings_give_identical_blocks(env, storage):
     for cfg, o, m in zip(settings, outs, moms):
         assert np.array_equal(o, outs[0]), cfg
         assert np.abs(m - moms[0]).max() < 1e-12 * np.abs(moms[0][0]).max(), cfg
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_automatic_order_on_wide_lattice(env, prec):
+    """A 128x128 plane puts 320 MiB of slab-major traffic between a site's
+    two z-neighbour gathers, so the default order runs the matrix-free step
+    as a z-march; the filtered block is bitwise the one of the explicit
+    slab-major and z-march orders."""
+    torch, B, ctx = env
+    H = B.Matrix.ti(ctx, (128, 128, 3), pbc=3, V=1.0, seed=4, storage=B.STORAGE_STENCIL)
+    info = H.info()
+    a, b = info["g_lo"], info["g_hi"]
+    n_s = 32 if prec == "c128" else 64
+    X0 = to_dev(torch, inp.random_block(info["n"], n_s, seed=8),
+                dtype=torch.complex64 if prec == "c64" else None)
+    gam = inp.random_gamma(5, seed=9)
+    outs = []
+    try:
+        for order in (-1, 0, 2):
+            B.chebfd_set_tuning(ctx, "order", order)
+            Xd = X0.clone()
+            Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
+            B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
+            torch.cuda.synchronize()
+            outs.append(Xd.cpu().numpy())
+    finally:
+        B.chebfd_set_tuning(ctx, "order", -1)
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+    assert np.isfinite(outs[0]).all() and np.abs(outs[0]).max() > 0
 
 
 def test_filter_full_block_equals_column_subset(env, orc):
