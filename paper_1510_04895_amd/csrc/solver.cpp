@@ -397,6 +397,14 @@ struct Solver {
                 const bool stalled = it >= 2 && ngood > 0 &&
                                      ngood <= prev_good + std::max(1, prev_good / 10) &&
                                      med > 0.5 * prev_worst;
+                if (p.verbose) {
+                    std::fprintf(stderr,
+                                 "chebfd: FP32 phase: %d in-window pairs below sqrt(eps), median "
+                                 "residual %.3e, largest %.3e, switch threshold %.3e%s\n",
+                                 ngood, med, mx, thr,
+                                 below ? " (below)" : stalled ? " (stalled)" : "");
+                    std::fflush(stderr);
+                }
                 prev_worst = ngood > 0 ? med : INFINITY;
                 prev_good = ngood;
                 if (below || stalled) {

@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--storage", default="stencil", choices=["sell", "stencil"])
     ap.add_argument("--forms", default="fp64,c64,c64_learned")
     ap.add_argument("--max-iter", type=int, default=40)
+    ap.add_argument("--polish-units", type=float, default=None,
+                    help="complex64 forms: FP64 switch threshold in units of 2^-23 S_w "
+                         "(default: the library's, 8 units)")
     ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
                     help="spectral interval: Gershgorin or 40 Lanczos steps (checked by the solver)")
     ap.add_argument("--plan-only", action="store_true",
@@ -80,6 +83,8 @@ def main():
     if args.bounds == "lanczos":
         lanczos_steps = 40
         a, b = B.chebfd_lanczos_bounds(ctx, H, k=lanczos_steps, seed=w["seeds"][0])
+    polish_switch = (float("nan") if args.polish_units is None
+                     else args.polish_units * 2.0**-23 * max(abs(a), abs(b)))
     mu_c = B.chebfd_kpm_moments(ctx, H, learned.N_VEC, N_MOM_COUNT, w["seeds"][0], a, b,
                                 precision=B.PREC_C64)
     mu = mu_c[:learned.N_MOM]
@@ -130,11 +135,12 @@ def main():
         torch.cuda.synchronize()
         r = learned.run_solve(ctx, H, delta, n_s, n_p, corr=corr, precision=prec,
                               max_iter=args.max_iter, seed=w["seeds"][0], verbose=1,
-                              bounds=lanczos_steps)
+                              bounds=lanczos_steps, polish_switch=polish_switch)
         row = dict(form=form, n_p=n_p, corrections=corr is not None, status=r["rc"],
                    found=r["found"], time_s=r["time"],
                    n_mvm=r["n_mvm"], iterations=r["iterations"],
-                   max_residual=float(r["res"].max()) if r["found"] else None)
+                   max_residual=float(r["res"].max()) if r["found"] else None,
+                   polish_units=args.polish_units)
         if form == "fp64":
             ref = r
         elif ref is not None and ref["found"] == r["found"] and r["found"]:
