@@ -388,8 +388,9 @@ typedef struct {
                                  corrections: gamma_n <- gamma_n (1 + corr_n) */
     double polish_switch;    /* C64 only: go to FP64 once every in-window
                                 residual below sqrt(eps) is below this, or
-                                their median stops halving with no new
-                                pair below sqrt(eps); NaN = 8 * 2^-23 * S_w
+                                their median is below half of it, or their
+                                median stops halving with no new pair below
+                                sqrt(eps); NaN = 8 * 2^-23 * S_w
                                 (S_w = max(|a|, |b|)).  The FP64 polish then
                                 filters only the in-window Ritz vectors and
                                 the nearest ones outside the window

@@ -387,10 +387,15 @@ struct Solver {
                     med = good_r[good_r.size() / 2];
                 }
                 const int ngood = nconv + nconving;
-                // default threshold: a few FP32 roundings of the spectral scale
+                // default threshold: a few FP32 roundings of the spectral scale.
+                // The sweep is done once every good residual is below it, or
+                // once their median is below half of it: the typical pair
+                // then sits at the FP32 rounding floor, where its residual is
+                // rounding noise that one FP64 pass filters out, and the few
+                // pairs above it converge in the same polish passes
                 const double sw = std::max(std::fabs(a), std::fabs(b));
                 const double thr = std::isnan(p.polish_switch) ? 8.0 * 0x1p-23 * sw : p.polish_switch;
-                const bool below = ngood > 0 && mx <= thr;
+                const bool below = ngood > 0 && (mx <= thr || med <= 0.5 * thr);
                 // stalled: the set of good pairs grew by at most 10% and their
                 // median residual no longer halves (the FP32 floor; a few
                 // slow pairs are left to the FP64 polish)
