@@ -88,3 +88,15 @@ def test_kpm_window_count_on_the_chebyshev_density():
         assert sr.kpm_count(mu, n, -1.0, 1.0, d) == pytest.approx(want, rel=2e-3)
     d = sr.window_for_count(mu, n, -1.0, 1.0, 100000)
     assert n * 2.0 / math.pi * math.asin(d) == pytest.approx(100000, rel=2e-3)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it exits with status 2
+    and says so, before touching a device."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
