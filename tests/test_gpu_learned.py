@@ -116,7 +116,7 @@ def test_trained_model_on_heldout_realisation(env, seed):
     gated by the damping-factor check, reach the same eigenvalues as the
     DOS rule's parameters at residual <= 1e-9.  The work bound is a sanity
     guard against a broken network or decoding (the held-out evaluation
-    saw ratios of matrix-vector products between 0.70 and 1.76 per
+    saw ratios of matrix-vector products between 0.70 and 1.8 per
     realisation), not a performance claim."""
     import os
     torch, B, ctx = env
