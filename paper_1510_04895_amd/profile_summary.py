@@ -9,6 +9,12 @@
            each scaled by what the same counter reads for the plain copy
            kernel of the bandwidth probe (2 GiB read + 2 GiB written), with
            the hash of the kernel sources the counters were taken on.
+    python -m paper_1510_04895_amd.profile_summary mfma PMC_DIR NAME "COMMAND"
+        -> profiles/NAME.md: per MFMA kernel, the FP64 MFMA flops per dispatch
+           (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512) and the MFMA busy share of all
+           SIMD cycles (SQ_VALU_MFMA_BUSY_CYCLES over the GPU-active cycles
+           times the SIMD count; the CSV carries GRBM_GUI_ACTIVE summed over
+           the XCDs, each of which counts the same cycles).
 """
 from __future__ import annotations
 
@@ -66,6 +72,36 @@ def traffic(storage, prec, workload, fdir, wdir, cmd_f, cmd_w):
     return out
 
 
+SIMDS = 256 * 4             # MI355X: 256 compute units of 4 SIMDs
+XCDS = 8                    # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs
+
+
+def mfma(pmc_dir, name, cmd, kernels=("k_gram", "k_block_times")):
+    vals = collections.defaultdict(list)
+    with open(_csv_in(pmc_dir)) as fh:
+        for r in csv.DictReader(fh):
+            vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    lines = [f"# {name}", "", "Command (from the repository root, TMPDIR=/tmp):", "",
+             "    " + cmd, "",
+             "| kernel | dispatches | FP64 MFMA flops per dispatch | MFMA busy, % of SIMD cycles |",
+             "|---|---:|---:|---:|"]
+    out = {}
+    for (k, c), v in sorted(vals.items()):
+        if c != "SQ_INSTS_VALU_MFMA_MOPS_F64" or not any(s in k for s in kernels):
+            continue
+        busy = sum(vals[(k, "SQ_VALU_MFMA_BUSY_CYCLES")])
+        gui = sum(vals[(k, "GRBM_GUI_ACTIVE")])
+        flops = sum(v) * 512 / len(v)
+        util = 100.0 * busy / (gui / XCDS * SIMDS) if gui > 0 else float("nan")
+        nm = k.replace("chebfd::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        out[nm] = dict(dispatches=len(v), flops_per_dispatch=flops, mfma_busy_pct=util)
+        lines.append(f"| `{nm}` | {len(v)} | {flops:.3e} | {util:.1f} |")
+    text = "\n".join(lines) + "\n"
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as fh:
+        fh.write(text)
+    return out
+
+
 def stats(path, name, cmd):
     with open(path) as fh:
         rows = list(csv.DictReader(fh))
@@ -91,5 +127,7 @@ if __name__ == "__main__":
         print(stats(*sys.argv[2:5]))
     elif what == "traffic":
         print(json.dumps(traffic(*sys.argv[2:9]), indent=1))
+    elif what == "mfma":
+        print(json.dumps(mfma(*sys.argv[2:5]), indent=1))
     else:
         raise SystemExit(__doc__)

@@ -100,3 +100,24 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
     assert r.stdout == ""
 
+
+
+def test_mfma_summary(tmp_path, monkeypatch):
+    """FP64 MFMA flops = MOPS x 512 per dispatch; busy share = busy cycles
+    summed over SIMDs over (GPU-active cycles x 1024 SIMDs), the active
+    cycles arriving summed over the 8 XCDs."""
+    from paper_1510_04895_amd import profile_summary as ps
+    g = "void chebfd::(anonymous namespace)::k_gram<double>(...)"
+    _write_pmc(tmp_path / "m", [(g, "SQ_INSTS_VALU_MFMA_MOPS_F64", 1000.0),
+                                (g, "SQ_INSTS_VALU_MFMA_MOPS_F64", 3000.0),
+                                (g, "SQ_VALU_MFMA_BUSY_CYCLES", 1024 * 50.0),
+                                (g, "SQ_VALU_MFMA_BUSY_CYCLES", 1024 * 30.0),
+                                (g, "GRBM_GUI_ACTIVE", 800.0), (g, "GRBM_GUI_ACTIVE", 800.0),
+                                ("k_copy16(...)", "SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)])
+    monkeypatch.setattr(ps, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    out = ps.mfma(str(tmp_path / "m"), "mfma_test", "cmd")
+    assert list(out) == ["k_gram<double>"]
+    assert out["k_gram<double>"]["flops_per_dispatch"] == pytest.approx(2000 * 512)
+    assert out["k_gram<double>"]["mfma_busy_pct"] == pytest.approx(40.0)
+    assert "| `k_gram<double>` | 2 |" in open(tmp_path / "profiles" / "mfma_test.md").read()
