@@ -30,14 +30,18 @@ __device__ __forceinline__ double ld_real(const T *p)
 // Real G_part[ks] = Z_A^T Z_B over rows [ks*rows, (ks+1)*rows).
 // Workgroup tile 64 (m) x 64 (n); four waves of 32 x 32, each 2 x 2 MFMA
 // blocks of 16 x 16; K (the row index of the tall blocks) staged 16 at a time
-// through LDS.  MFMA f64 16x16x4 operand layout (measured on gfx950): lane l
+// through LDS, the next stage's global loads issued into registers before the
+// current stage's MFMAs (their latency overlaps the matrix work; the
+// accumulation order is unchanged; a register budget for 4 waves per SIMD
+// keeps the occupancy the version without prefetch had).  MFMA f64 16x16x4
+// operand layout (measured on gfx950): lane l
 // holds A[m = l%16][k = l/16] and B[k = l/16][n = l%16]; result register r
 // of lane l is D[m = l/16 + 4r][n = l%16].
 constexpr int GT = 64;   // tile
 constexpr int GK = 16;   // rows per LDS stage
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ A, int64_t lda2, int64_t ma,
+__global__ __launch_bounds__(256, 4) void k_gram(const T *__restrict__ A, int64_t lda2, int64_t ma,
                                               const T *__restrict__ B, int64_t ldb2, int64_t mb,
                                               int64_t n, int64_t rows_per_split,
                                               double *__restrict__ part)
@@ -55,17 +59,29 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ A, int64_t l
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t rb = r0; rb < r1; rb += GK) {
+    constexpr int PER = (GK * GT) / 256;
+    double pa[PER], pb[PER];
+    auto fetch = [&](int64_t s0) {
 #pragma unroll
-        for (int q = 0; q < (GK * GT) / 256; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const int idx = tid + 256 * q;
             const int kk = idx / GT, mm = idx % GT;
-            const int64_t row = rb + kk;
+            const int64_t row = s0 + kk;
             const bool rv = row < r1;
-            As[kk][mm] = (rv && m0 + mm < ma) ? ld_real(A + row * lda2 + m0 + mm) : 0.0;
-            Bs[kk][mm] = (rv && n0 + mm < mb) ? ld_real(B + row * ldb2 + n0 + mm) : 0.0;
+            pa[q] = (rv && m0 + mm < ma) ? ld_real(A + row * lda2 + m0 + mm) : 0.0;
+            pb[q] = (rv && n0 + mm < mb) ? ld_real(B + row * ldb2 + n0 + mm) : 0.0;
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t rb = r0; rb < r1; rb += GK) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q;
+            As[idx / GT][idx % GT] = pa[q];
+            Bs[idx / GT][idx % GT] = pb[q];
         }
         __syncthreads();
+        if (rb + GK < r1) fetch(rb + GK);
 #pragma unroll
         for (int k4 = 0; k4 < GK; k4 += 4) {
             const int kk = k4 + (lane >> 4);
@@ -119,7 +135,7 @@ __global__ void k_gram_reduce(const double *__restrict__ part, int64_t ks_count,
 // C (n x mc real) = Z_A (n x ka real) Treal (ka x mc), or C -= Z_A Treal.
 // Workgroup tile 64 rows x 64 columns; waves 32 x 32 as in the Gram.
 template <typename TA, typename TC, bool SUB>
-__global__ __launch_bounds__(256) void k_block_times(const TA *__restrict__ A, int64_t lda2,
+__global__ __launch_bounds__(256, 4) void k_block_times(const TA *__restrict__ A, int64_t lda2,
                                                      int64_t n, int64_t ka,
                                                      const double *__restrict__ Tr, int64_t mc,
                                                      TC *C, int64_t ldc2, int64_t ntile_c)
@@ -135,20 +151,33 @@ __global__ __launch_bounds__(256) void k_block_times(const TA *__restrict__ A, i
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t kb = 0; kb < ka; kb += GK) {
+    constexpr int PER = (GK * GT) / 256;
+    double pa[PER], pt[PER];
+    // next stage into registers, issued before the current stage's MFMAs
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < (GK * GT) / 256; ++q) {
+        for (int q = 0; q < PER; ++q) {
             const int idx = tid + 256 * q;
             // A tile: 64 rows x 16 k, read 16 consecutive doubles per row
             const int ii = idx / GK, kk = idx % GK;
-            const int64_t row = i0 + ii, kc = kb + kk;
-            As[ii][kk] = (row < n && kc < ka) ? (double)A[row * lda2 + kc] : 0.0;
+            const int64_t row = i0 + ii, kc = k0 + kk;
+            pa[q] = (row < n && kc < ka) ? (double)A[row * lda2 + kc] : 0.0;
             // T tile: 16 k x 64 columns
             const int tk = idx / GT, tm = idx % GT;
-            const int64_t kr = kb + tk, cc = c0 + tm;
-            Ts[tk][tm] = (kr < ka && cc < mc) ? Tr[kr * mc + cc] : 0.0;
+            const int64_t kr = k0 + tk, cc = c0 + tm;
+            pt[q] = (kr < ka && cc < mc) ? Tr[kr * mc + cc] : 0.0;
+        }
+    };
+    if (ka > 0) fetch(0);
+    for (int64_t kb = 0; kb < ka; kb += GK) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q;
+            As[idx / GK][idx % GK] = pa[q];
+            Ts[idx / GT][idx % GT] = pt[q];
         }
         __syncthreads();
+        if (kb + GK < ka) fetch(kb + GK);
 #pragma unroll
         for (int k4 = 0; k4 < GK; k4 += 4) {
             const int kk = k4 + (lane >> 4);
