@@ -257,6 +257,13 @@ def main():
             "solve_stats": {k: (round(v, 4) if isinstance(v, float) else v)
                             for k, v in stats.items()},
             "fused_kernel_tflops": round(step_flops(n, n_s, nnz_row) / t_launch / 1e12, 3),
+            # the paper's own filter-step rate on a CPU cluster (Table
+            # tab:benchmark, largest TI run): another machine and a 2000x
+            # larger matrix, so context for the flop/s figure, not a target
+            "paper_context": {"value": 43.9, "unit": "Tflop/s", "per_node": 0.0857,
+                              "system": "512 CPU nodes, two 14-core Xeon E5-2697v3 each",
+                              "workload": "TI matrix, D = 1.07e9, N_S = 256, N_p = 8639",
+                              "flop_convention": "same complex counting (Sec. 4.2)"},
         })
     # the same solve on Lanczos bounds instead of Gershgorin's (Sec. 3.1
     # step 1): same eigenpairs, a ~1.5x lower filter degree
