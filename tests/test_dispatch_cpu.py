@@ -5,6 +5,7 @@ is compiled for the host (its device qualifiers defined away) and checked
 exhaustively on small grids and on the grid sizes of the throughput
 configurations."""
 import os
+import re
 import shutil
 import subprocess
 
@@ -61,3 +62,28 @@ def test_xcd_remap_is_a_bijection(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout
     assert r.stdout.strip() == "ok"
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle and the HIP path are independent: no library source
+    includes or names the oracle, no oracle source includes the library's
+    headers or imports its package, and the product package never imports
+    the oracle (only tests, the smoke check and the benchmark's CPU
+    baseline do)."""
+    pkg = os.path.join(ROOT, "paper_1510_04895_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if not f.endswith((".py", ".cpp", ".hip", ".h", ".c")):
+                continue
+            text = open(os.path.join(dp, f), encoding="utf-8").read()
+            assert "import oracle" not in text and "from oracle" not in text, f
+            assert "chebfd_oracle" not in text and "liboracle" not in text, f
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if not f.endswith((".py", ".c", ".h")):
+            continue
+        text = open(os.path.join(odir, f), encoding="utf-8").read()
+        assert "import paper_1510_04895_amd" not in text, f
+        assert "from paper_1510_04895_amd" not in text, f
+        assert not re.search(r'#\s*include\s*[<"][^>"]*(chebfd|internal|pack|dispatch)\.h', text), f
+        assert "libchebfd" not in text, f
