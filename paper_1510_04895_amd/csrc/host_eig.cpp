@@ -5,7 +5,9 @@
 // a diagonal unitary D making the subdiagonal real (T = D Tr D^H), the
 // implicit QL iteration with Wilkinson shifts on the real tridiagonal Tr
 // (Bowdler, Martin, Reinsch and Wilkinson, Numer. Math. 11, 1968), and the
-// eigenvectors Q D Z.  O(n^3), about 10 n^3 flops.
+// eigenvectors Q D Z, with Q applied as its stored reflectors.  O(n^3).  The
+// complex matrices are kept as separate real and imaginary planes so the
+// inner loops are plain FMA streams.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -20,66 +22,127 @@ using cd = std::complex<double>;
 
 namespace {
 
-// Householder tridiagonalisation in place; Q accumulates the reflectors.
-void tridiagonalise(int n, std::vector<cd> &A, std::vector<cd> &Q)
+// Householder tridiagonalisation in place on split real/imaginary planes
+// (Ar, Ai row-major n x n).  Step k maps column k below the diagonal onto
+// alpha e_1 with H_k = I - tau_k v_k v_k^H; v_k (m = n - k - 1 entries) goes
+// to row k of (Vr, Vi) from column k + 1 on, tau_k to tau[k] (0: no
+// reflection).  A = Q T Q^H with Q = H_0 H_1 ... H_{n-3}.
+void tridiagonalise(int n, std::vector<double> &Ar, std::vector<double> &Ai,
+                    std::vector<double> &Vr, std::vector<double> &Vi, std::vector<double> &tau)
 {
-    Q.assign((size_t)n * n, cd(0.0));
-    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
-    std::vector<cd> v(n), p(n), q(n);
+    Vr.assign((size_t)n * n, 0.0);
+    Vi.assign((size_t)n * n, 0.0);
+    tau.assign(n, 0.0);
+    std::vector<double> pr(n), pi(n), qr(n), qi(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
+        double *__restrict__ vr = &Vr[(size_t)k * n + k + 1];
+        double *__restrict__ vi = &Vi[(size_t)k * n + k + 1];
         double xn = 0.0;
-        for (int i = 0; i < m; ++i) xn += std::norm(A[(size_t)(k + 1 + i) * n + k]);
+        for (int i = 0; i < m; ++i) {
+            vr[i] = Ar[(size_t)(k + 1 + i) * n + k];
+            vi[i] = Ai[(size_t)(k + 1 + i) * n + k];
+            xn += vr[i] * vr[i] + vi[i] * vi[i];
+        }
         xn = std::sqrt(xn);
         if (xn == 0.0) continue;
-        const cd x0 = A[(size_t)(k + 1) * n + k];
-        const cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
-        const cd alpha = -ph * xn;            // H x = alpha e_1
-        for (int i = 0; i < m; ++i) v[i] = A[(size_t)(k + 1 + i) * n + k];
-        v[0] -= alpha;
+        const double ax = std::hypot(vr[0], vi[0]);
+        const double phr = ax > 0.0 ? vr[0] / ax : 1.0, phi = ax > 0.0 ? vi[0] / ax : 0.0;
+        const double alr = -phr * xn, ali = -phi * xn;   // H x = alpha e_1
+        vr[0] -= alr;
+        vi[0] -= ali;
         double vn2 = 0.0;
-        for (int i = 0; i < m; ++i) vn2 += std::norm(v[i]);
+        for (int i = 0; i < m; ++i) vn2 += vr[i] * vr[i] + vi[i] * vi[i];
         if (vn2 == 0.0) continue;
-        const double tau = 2.0 / vn2;         // H = I - tau v v^H
-        // p = tau A22 v ; K = tau/2 v^H p ; q = p - K v ; A22 -= v q^H + q v^H
+        const double t = 2.0 / vn2;
+        tau[k] = t;
+        // p = tau A22 v ; K = tau/2 v^H p (real) ; q = p - K v ;
+        // A22 -= v q^H + q v^H
         for (int i = 0; i < m; ++i) {
-            cd s = 0.0;
-            const cd *row = &A[(size_t)(k + 1 + i) * n + k + 1];
-            for (int j = 0; j < m; ++j) s += row[j] * v[j];
-            p[i] = tau * s;
+            const double *__restrict__ rr = &Ar[(size_t)(k + 1 + i) * n + k + 1];
+            const double *__restrict__ ri = &Ai[(size_t)(k + 1 + i) * n + k + 1];
+            double sr = 0.0, si = 0.0;
+            for (int j = 0; j < m; ++j) {
+                sr += rr[j] * vr[j] - ri[j] * vi[j];
+                si += rr[j] * vi[j] + ri[j] * vr[j];
+            }
+            pr[i] = t * sr;
+            pi[i] = t * si;
         }
-        cd K = 0.0;
-        for (int i = 0; i < m; ++i) K += std::conj(v[i]) * p[i];
-        K *= 0.5 * tau;
-        for (int i = 0; i < m; ++i) q[i] = p[i] - K.real() * v[i];
+        double K = 0.0;
+        for (int i = 0; i < m; ++i) K += vr[i] * pr[i] + vi[i] * pi[i];
+        K *= 0.5 * t;
         for (int i = 0; i < m; ++i) {
-            cd *row = &A[(size_t)(k + 1 + i) * n + k + 1];
-            for (int j = 0; j < m; ++j) row[j] -= v[i] * std::conj(q[j]) + q[i] * std::conj(v[j]);
+            qr[i] = pr[i] - K * vr[i];
+            qi[i] = pi[i] - K * vi[i];
         }
-        A[(size_t)(k + 1) * n + k] = alpha;
-        A[(size_t)k * n + k + 1] = std::conj(alpha);
+        for (int i = 0; i < m; ++i) {
+            double *__restrict__ rr = &Ar[(size_t)(k + 1 + i) * n + k + 1];
+            double *__restrict__ ri = &Ai[(size_t)(k + 1 + i) * n + k + 1];
+            const double a = vr[i], b = vi[i], c = qr[i], d = qi[i];
+            for (int j = 0; j < m; ++j) {
+                // v_i conj(q_j) + q_i conj(v_j)
+                rr[j] -= a * qr[j] + b * qi[j] + c * vr[j] + d * vi[j];
+                ri[j] -= b * qr[j] - a * qi[j] + d * vr[j] - c * vi[j];
+            }
+        }
+        Ar[(size_t)(k + 1) * n + k] = alr;
+        Ai[(size_t)(k + 1) * n + k] = ali;
+        Ar[(size_t)k * n + k + 1] = alr;
+        Ai[(size_t)k * n + k + 1] = -ali;
         for (int i = 1; i < m; ++i) {
-            A[(size_t)(k + 1 + i) * n + k] = 0.0;
-            A[(size_t)k * n + k + 1 + i] = 0.0;
-        }
-        // Q <- Q H
-        for (int r = 0; r < n; ++r) {
-            cd *row = &Q[(size_t)r * n + k + 1];
-            cd s = 0.0;
-            for (int j = 0; j < m; ++j) s += row[j] * v[j];
-            s *= tau;
-            for (int j = 0; j < m; ++j) row[j] -= s * std::conj(v[j]);
+            Ar[(size_t)(k + 1 + i) * n + k] = Ai[(size_t)(k + 1 + i) * n + k] = 0.0;
+            Ar[(size_t)k * n + k + 1 + i] = Ai[(size_t)k * n + k + 1 + i] = 0.0;
         }
     }
 }
 
 // Implicit QL on the real symmetric tridiagonal (d, e), e[i] coupling i and
 // i+1.  The rotations are accumulated into Zt, the transpose of the
-// eigenvector matrix (row i of Zt = eigenvector column i), so each rotation
-// updates two contiguous rows.
+// eigenvector matrix (row i of Zt = eigenvector column i).  One sweep's
+// rotations act on rows (i, i+1) for i = m-1 down to lo in turn; they are
+// recorded and then applied chunk of columns by chunk, the row carried from
+// one rotation to the next kept in registers.
+// Applies the rotations i = m-1 .. lo of one sweep to rows lo .. m of Zt:
+// rows (i, i+1) <- (c z_i - s z_{i+1}, s z_i + c z_{i+1}).  Row i+1 is final
+// after rotation i; the new row i is carried into rotation i-1.
+void apply_sweep(int n, int lo, int m, const double *rc, const double *rs, double *Zt)
+{
+    if (lo >= m) return;
+    constexpr int CB = 16;
+    for (int k0 = 0; k0 < n; k0 += CB) {
+        const int w = std::min(CB, n - k0);
+        double carry[CB];
+        const double *zm = Zt + (size_t)m * n + k0;
+        for (int k = 0; k < w; ++k) carry[k] = zm[k];
+        for (int i = m - 1; i >= lo; --i) {
+            const double s = rs[i], c = rc[i];
+            const double *zi = Zt + (size_t)i * n + k0;
+            double *zo = Zt + (size_t)(i + 1) * n + k0;
+            if (w == CB) {
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const double a = zi[k], cj = carry[k];
+                    zo[k] = s * a + c * cj;
+                    carry[k] = c * a - s * cj;
+                }
+            } else {
+                for (int k = 0; k < w; ++k) {
+                    const double a = zi[k], cj = carry[k];
+                    zo[k] = s * a + c * cj;
+                    carry[k] = c * a - s * cj;
+                }
+            }
+        }
+        double *zl = Zt + (size_t)lo * n + k0;
+        for (int k = 0; k < w; ++k) zl[k] = carry[k];
+    }
+}
+
 int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt)
 {
     const double eps = 2.220446049250313e-16;
+    std::vector<double> rc(n), rs(n);
     e.resize(n);
     e[n - 1] = 0.0;
     for (int l = 0; l < n; ++l) {
@@ -98,6 +161,7 @@ int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::v
             g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
             double s = 1.0, c = 1.0, p = 0.0;
             bool split = false;
+            int lo = m;   // rows lo .. m were rotated in this sweep
             for (int i = m - 1; i >= l; --i) {
                 const double f = s * e[i], bb = c * e[i];
                 r = std::hypot(f, g);
@@ -115,13 +179,11 @@ int tridiagonal_ql(int n, std::vector<double> &d, std::vector<double> &e, std::v
                 p = s * r;
                 d[i + 1] = g + p;
                 g = c * r - bb;
-                double *zi = &Zt[(size_t)i * n], *zj = &Zt[(size_t)(i + 1) * n];
-                for (int k = 0; k < n; ++k) {
-                    const double zf = zj[k];
-                    zj[k] = s * zi[k] + c * zf;
-                    zi[k] = c * zi[k] - s * zf;
-                }
+                rs[i] = s;
+                rc[i] = c;
+                lo = i;
             }
+            apply_sweep(n, lo, m, rc.data(), rs.data(), Zt.data());
             if (split) continue;
             d[l] -= p;
             e[l] = g;
@@ -137,51 +199,87 @@ int herm_eig(int n, std::vector<double> &Ain, std::vector<double> &w)
 {
     w.assign(n, 0.0);
     if (n == 0) return 0;
-    std::vector<cd> A((size_t)n * n), Q;
-    for (size_t i = 0; i < (size_t)n * n; ++i) A[i] = cd(Ain[2 * i], Ain[2 * i + 1]);
-    // enforce exact Hermitian symmetry of the input
+    const size_t nn = (size_t)n * n;
+    std::vector<double> Ar(nn), Ai(nn), Vr, Vi, tau;
+    // split planes with exact Hermitian symmetry of the input
     for (int i = 0; i < n; ++i) {
-        A[(size_t)i * n + i] = A[(size_t)i * n + i].real();
+        Ar[(size_t)i * n + i] = Ain[2 * ((size_t)i * n + i)];
+        Ai[(size_t)i * n + i] = 0.0;
         for (int j = i + 1; j < n; ++j) {
-            const cd v = 0.5 * (A[(size_t)i * n + j] + std::conj(A[(size_t)j * n + i]));
-            A[(size_t)i * n + j] = v;
-            A[(size_t)j * n + i] = std::conj(v);
+            const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+            const double re = 0.5 * (Ain[2 * ij] + Ain[2 * ji]);
+            const double im = 0.5 * (Ain[2 * ij + 1] - Ain[2 * ji + 1]);
+            Ar[ij] = re;
+            Ai[ij] = im;
+            Ar[ji] = re;
+            Ai[ji] = -im;
         }
     }
-    tridiagonalise(n, A, Q);
-    std::vector<double> d(n), e(n, 0.0);
-    std::vector<cd> delta(n, cd(1.0));
-    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i].real();
+    tridiagonalise(n, Ar, Ai, Vr, Vi, tau);
+    std::vector<double> d(n), e(n, 0.0), dr(n, 1.0), di(n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = Ar[(size_t)i * n + i];
     for (int i = 0; i + 1 < n; ++i) {
-        const cd sub = A[(size_t)(i + 1) * n + i];
-        const double a = std::abs(sub);
+        const double sr = Ar[(size_t)(i + 1) * n + i], si = Ai[(size_t)(i + 1) * n + i];
+        const double a = std::hypot(sr, si);
         e[i] = a;
-        delta[i + 1] = a > 0.0 ? delta[i] * (sub / a) : delta[i];
+        // delta_{i+1} = delta_i * sub / |sub|
+        if (a > 0.0) {
+            dr[i + 1] = (dr[i] * sr - di[i] * si) / a;
+            di[i + 1] = (dr[i] * si + di[i] * sr) / a;
+        } else {
+            dr[i + 1] = dr[i];
+            di[i + 1] = di[i];
+        }
     }
-    std::vector<double> Zt((size_t)n * n, 0.0);
+    std::vector<double> Zt(nn, 0.0);
     for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
     if (tridiagonal_ql(n, d, e, Zt) != 0) return -1;
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
-    // V = Q D Z, columns in ascending eigenvalue order:
-    // V[r][j] = sum_i (Q D)[r][i] Zt[ord j][i]
-    std::vector<cd> QD((size_t)n * n);
-    for (int r = 0; r < n; ++r)
-        for (int i = 0; i < n; ++i) QD[(size_t)r * n + i] = Q[(size_t)r * n + i] * delta[i];
     for (int j = 0; j < n; ++j) w[j] = d[ord[j]];
-    for (int r = 0; r < n; ++r) {
-        const cd *qr = &QD[(size_t)r * n];
+    // W = D Z with the columns in ascending eigenvalue order (Ar, Ai reused)
+    std::vector<double> &Wr = Ar, &Wi = Ai;
+    for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
-            const double *z = &Zt[(size_t)ord[j] * n];
-            double sr = 0.0, si = 0.0;
-            for (int i = 0; i < n; ++i) {
-                sr += qr[i].real() * z[i];
-                si += qr[i].imag() * z[i];
-            }
-            Ain[2 * ((size_t)r * n + j)] = sr;
-            Ain[2 * ((size_t)r * n + j) + 1] = si;
+            const double z = Zt[(size_t)ord[j] * n + i];
+            Wr[(size_t)i * n + j] = dr[i] * z;
+            Wi[(size_t)i * n + j] = di[i] * z;
         }
+    // V = H_0 H_1 ... H_{n-3} W, the reflectors applied last first to rows
+    // k+1 .. n-1: W <- W - tau v (v^H W)
+    std::vector<double> sr(n), si(n);
+    for (int k = n - 3; k >= 0; --k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        const int m = n - k - 1;
+        const double *vr = &Vr[(size_t)k * n + k + 1], *vi = &Vi[(size_t)k * n + k + 1];
+        std::fill(sr.begin(), sr.end(), 0.0);
+        std::fill(si.begin(), si.end(), 0.0);
+        double *__restrict__ s_r = sr.data();
+        double *__restrict__ s_i = si.data();
+        for (int i = 0; i < m; ++i) {
+            const double *__restrict__ wr = &Wr[(size_t)(k + 1 + i) * n];
+            const double *__restrict__ wi = &Wi[(size_t)(k + 1 + i) * n];
+            const double a = vr[i], b = vi[i];
+            for (int j = 0; j < n; ++j) {
+                s_r[j] += a * wr[j] + b * wi[j];   // conj(v_i) W_ij
+                s_i[j] += a * wi[j] - b * wr[j];
+            }
+        }
+        for (int i = 0; i < m; ++i) {
+            double *__restrict__ wr = &Wr[(size_t)(k + 1 + i) * n];
+            double *__restrict__ wi = &Wi[(size_t)(k + 1 + i) * n];
+            const double a = t * vr[i], b = t * vi[i];
+            for (int j = 0; j < n; ++j) {
+                wr[j] -= a * s_r[j] - b * s_i[j];
+                wi[j] -= a * s_i[j] + b * s_r[j];
+            }
+        }
+    }
+    for (size_t q = 0; q < nn; ++q) {
+        Ain[2 * q] = Wr[q];
+        Ain[2 * q + 1] = Wi[q];
     }
     return 0;
 }
