@@ -93,3 +93,40 @@ def test_solve_full_size(env, orc):
     assert rc2 == 0 and ev2.size == ev.size
     assert np.abs(ev2 - ev).max() < 1e-10 * S_w
     assert rs2.max() <= 1e-9
+
+
+def test_precision_form_solve_128x128x64(orc):
+    """The precision form at its full size (128x128x64, N = 4,194,304, N_S
+    256, complex64 sweep + FP64 polish, 40-step Lanczos interval, window of
+    half-width 0.1335 holding about 100 eigenvalues): every returned pair
+    has a residual <= 1e-9 when the reference recomputes H v - lambda v with
+    its own sparse product, the vectors are orthonormal, and the eigenvalues
+    lie in the window and come in Kramers pairs."""
+    import torch
+    from paper_1510_04895_amd import binding as B
+    W3 = inp.WORKLOADS["ti_128x128x64"]
+    ctx = B.Context(0)
+    H = B.Matrix.ti(ctx, W3["L"], pbc=W3["pbc"], V=W3["V"], seed=W3["seeds"][0],
+                    storage=B.STORAGE_STENCIL)
+    a, b = B.chebfd_lanczos_bounds(ctx, H, k=40, seed=W3["seeds"][0])
+    d = 0.1335
+    dp = d * (math.sqrt(W3["n_s"] / W3["n_target"]) - 1.0)
+    n_p, _ = B.chebfd_optimal_np(a, b, -d, d, -d - dp, d + dp)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=W3["n_s"], n_p=n_p, kernel=W3["kernel"],
+                         mu=W3["mu"], eps=W3["eps"], max_iter=40, lock=1,
+                         precision=B.PREC_C64, seed=W3["seeds"][0], vectors=1, bounds=40)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    del H
+    torch.cuda.empty_cache()
+    assert rc == 0, stats
+    assert 90 <= ev.size <= 110 and ev.size % 2 == 0, ev.size
+    assert np.all(np.abs(ev) <= d) and np.all(np.diff(ev) >= 0)
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert np.abs(ev[0::2] - ev[1::2]).max() < 1e-10 * S_w
+    Hr = orc.ti_hamiltonian(*W3["L"], pbc=W3["pbc"], V=W3["V"], seed=W3["seeds"][0])
+    HV = orc.spmm(Hr, V)
+    r = np.linalg.norm(HV - V * ev, axis=0)
+    assert r.max() <= 1e-9, r.max()
+    assert np.abs(r - rs).max() < 1e-11
+    G = V.conj().T @ V
+    assert np.abs(G - np.eye(ev.size)).max() < 1e-10
