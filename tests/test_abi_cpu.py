@@ -157,3 +157,25 @@ def test_learned_features_layout(B):
     f = B.chebfd_learned_features(mu, -4.0, 4.0, -0.4, 0.2)
     assert f.dtype == np.float32 and f.size == 12
     assert np.allclose(f[:10], mu) and np.allclose(f[10:], [-0.1, 0.05])
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library every call raises (there is no CPU
+    fallback): checked in a fresh interpreter with the library path pointed
+    at a file that does not exist."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1510_04895_amd import binding as B\n"
+        "B.LIB_PATH = %r\n"
+        "B._lib = None\n"
+        "try:\n"
+        "    B.chebfd_coeffs(-0.1, 0.1, -1.0, 1.0, 16)\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n") % (ROOT, str(tmp_path / "libchebfd.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "is missing" in r.stdout and "no CPU fallback" in r.stdout
