@@ -26,7 +26,9 @@ namespace {
 // (Ar, Ai row-major n x n).  Step k maps column k below the diagonal onto
 // alpha e_1 with H_k = I - tau_k v_k v_k^H; v_k (m = n - k - 1 entries) goes
 // to row k of (Vr, Vi) from column k + 1 on, tau_k to tau[k] (0: no
-// reflection).  A = Q T Q^H with Q = H_0 H_1 ... H_{n-3}.
+// reflection).  A = Q T Q^H with Q = H_0 H_1 ... H_{n-3}.  Only the lower
+// triangle of the trailing block is read and updated (A is Hermitian); the
+// tridiagonal is left in the diagonal and the first subdiagonal.
 void tridiagonalise(int n, std::vector<double> &Ar, std::vector<double> &Ai,
                     std::vector<double> &Vr, std::vector<double> &Vi, std::vector<double> &tau)
 {
@@ -58,16 +60,29 @@ void tridiagonalise(int n, std::vector<double> &Ar, std::vector<double> &Ai,
         tau[k] = t;
         // p = tau A22 v ; K = tau/2 v^H p (real) ; q = p - K v ;
         // A22 -= v q^H + q v^H
+        // p = A22 v from the lower triangle: row i gives A_ij v_j (j < i) to
+        // p_i and conj(A_ij) v_i to p_j; the diagonal is real
+        std::fill(pr.begin(), pr.begin() + m, 0.0);
+        std::fill(pi.begin(), pi.begin() + m, 0.0);
+        double *__restrict__ p_r = pr.data();
+        double *__restrict__ p_i = pi.data();
         for (int i = 0; i < m; ++i) {
             const double *__restrict__ rr = &Ar[(size_t)(k + 1 + i) * n + k + 1];
             const double *__restrict__ ri = &Ai[(size_t)(k + 1 + i) * n + k + 1];
+            const double a = vr[i], b = vi[i];
             double sr = 0.0, si = 0.0;
-            for (int j = 0; j < m; ++j) {
+            for (int j = 0; j < i; ++j) {
                 sr += rr[j] * vr[j] - ri[j] * vi[j];
                 si += rr[j] * vi[j] + ri[j] * vr[j];
+                p_r[j] += rr[j] * a + ri[j] * b;
+                p_i[j] += rr[j] * b - ri[j] * a;
             }
-            pr[i] = t * sr;
-            pi[i] = t * si;
+            p_r[i] += sr + rr[i] * a;
+            p_i[i] += si + rr[i] * b;
+        }
+        for (int i = 0; i < m; ++i) {
+            pr[i] *= t;
+            pi[i] *= t;
         }
         double K = 0.0;
         for (int i = 0; i < m; ++i) K += vr[i] * pr[i] + vi[i] * pi[i];
@@ -80,7 +95,7 @@ void tridiagonalise(int n, std::vector<double> &Ar, std::vector<double> &Ai,
             double *__restrict__ rr = &Ar[(size_t)(k + 1 + i) * n + k + 1];
             double *__restrict__ ri = &Ai[(size_t)(k + 1 + i) * n + k + 1];
             const double a = vr[i], b = vi[i], c = qr[i], d = qi[i];
-            for (int j = 0; j < m; ++j) {
+            for (int j = 0; j <= i; ++j) {
                 // v_i conj(q_j) + q_i conj(v_j)
                 rr[j] -= a * qr[j] + b * qi[j] + c * vr[j] + d * vi[j];
                 ri[j] -= b * qr[j] - a * qi[j] + d * vr[j] - c * vi[j];
