@@ -68,8 +68,6 @@ def lib():
         L.orc_kernel.argtypes = [i32, i32, dbl, vp]
         L.orc_poly_eval.restype = dbl
         L.orc_poly_eval.argtypes = [vp, i32, dbl, dbl, dbl]
-        L.orc_filter_quality.restype = dbl
-        L.orc_filter_quality.argtypes = [vp, i32, dbl, dbl, dbl, dbl, dbl, dbl, i32, vp]
         L.orc_filter.restype = i32
         L.orc_filter.argtypes = [i64, vp, vp, vp, dbl, dbl, vp, i32, vp, vp, vp, i64, vp]
         L.orc_moments_direct.argtypes = [i64, vp, vp, vp, dbl, dbl, vp, i64, i32, vp]
@@ -199,25 +197,13 @@ def poly_eval(gam, a, b, lam) -> float:
 
 
 def filter_quality(gam, a, b, t_lo, t_hi, s_lo, s_hi, pts_per_period=16):
-    """(sigma, eta) of Sec. 2.3 for the polynomial with coefficients gam."""
-    gam = np.ascontiguousarray(gam, np.float64)
-    eta = C.c_double()
-    sigma = lib().orc_filter_quality(_p(gam), gam.size - 1, a, b, t_lo, t_hi, s_lo, s_hi,
-                                     pts_per_period, C.byref(eta))
-    return sigma, eta.value
-
-
-def eta_of_np(n_p, a, b, t_lo, t_hi, s_lo, s_hi, kind="lanczos", mu=2.0, pts=16):
-    g = gamma(t_lo, t_hi, a, b, n_p, kind, mu)
-    return filter_quality(g, a, b, t_lo, t_hi, s_lo, s_hi, pts)[1]
-
-
-def filter_quality_dct(gam, a, b, t_lo, t_hi, s_lo, s_hi, pts_per_period=16):
-    """(sigma, eta) of Sec. 2.3 with p evaluated on the uniform theta grid
-    theta_k = pi k / M by one type-I discrete cosine transform (a library
-    FFT), p(cos theta_k) = sum_n gamma_n cos(n theta_k); the four interval
-    edges are evaluated by the recurrence.  Same definition as
-    filter_quality, different evaluation."""
+    """(sigma, eta) of Sec. 2.3: sigma = max |p| over [a, b] outside the
+    search interval [s_lo, s_hi] divided by min |p| over the target
+    [t_lo, t_hi], eta = -N_p / log10(sigma).  p is evaluated on the uniform
+    theta grid theta_k = pi k / M (x = cos theta_k, pts_per_period points
+    per period of T_{N_p}) by one type-I discrete cosine transform (a
+    library FFT), p(cos theta_k) = sum_n gamma_n cos(n theta_k); the four
+    interval edges are evaluated by the recurrence."""
     from scipy.fft import dct
     gam = np.asarray(gam, np.float64)
     n_p = gam.size - 1
@@ -241,7 +227,7 @@ def filter_quality_dct(gam, a, b, t_lo, t_hi, s_lo, s_hi, pts_per_period=16):
 
 def eta_of_np(n_p, a, b, t_lo, t_hi, s_lo, s_hi, kind="lanczos", mu=2.0, pts=16):
     g = gamma(t_lo, t_hi, a, b, n_p, kind, mu)
-    return filter_quality_dct(g, a, b, t_lo, t_hi, s_lo, s_hi, pts)[1]
+    return filter_quality(g, a, b, t_lo, t_hi, s_lo, s_hi, pts)[1]
 
 
 def optimal_np(a, b, t_lo, t_hi, s_lo, s_hi, kind="lanczos", mu=2.0, lo=None, hi=None, pts=16):
@@ -277,6 +263,66 @@ def optimal_np(a, b, t_lo, t_hi, s_lo, s_hi, kind="lanczos", mu=2.0, lo=None, hi
             ev(j)
     best = min(f, key=lambda k: f[k])
     return best, f[best]
+
+
+# density of states from KPM moments (Sec. 3.1 steps 1-3) --------------------
+def kpm_density(mu, a, b, lam):
+    """KPM estimate of the normalised DOS at lam (per unit lambda, integral
+    1 over [a, b]) from moments mu_m = <T_m(alpha H + beta)>/D, m < M:
+    rho(x) = [g_0 mu_0 + 2 sum_{m>=1} g_m mu_m T_m(x)] / (pi sqrt(1 - x^2))
+    in the scaled variable x, with the Jackson factors of Table tab:Kernel
+    at N_p = M (so g_{M-1} = 0), times dx/dlambda = 2/(b - a)."""
+    mu = np.asarray(mu, np.float64)
+    M = mu.size
+    g = kernel("jackson", M)[:M]
+    x = (2.0 * np.asarray(lam, np.float64) - a - b) / (b - a)
+    th = np.arccos(np.clip(x, -1.0, 1.0))
+    m = np.arange(1, M)
+    s = g[0] * mu[0] + 2.0 * (g[1:] * mu[1:] * np.cos(np.multiply.outer(th, m))).sum(-1)
+    return s / (np.pi * np.sqrt(1.0 - x * x)) * 2.0 / (b - a)
+
+
+def dos_count(mu, D, a, b, lo, hi):
+    """Eq. DOS:target with the KPM density: D times the integral of rho over
+    [lo, hi] (clipped to [a, b]), integrated numerically in theta = acos(x),
+    where d lambda rho = (1/pi) [g_0 mu_0 + 2 sum g_m mu_m cos(m theta)]
+    d theta, by composite 8-point Gauss-Legendre quadrature with one panel
+    per 1/(2M) of the theta range of a full period."""
+    mu = np.asarray(mu, np.float64)
+    M = mu.size
+    g = kernel("jackson", M)[:M]
+    xl = np.clip((2.0 * lo - a - b) / (b - a), -1.0, 1.0)
+    xh = np.clip((2.0 * hi - a - b) / (b - a), -1.0, 1.0)
+    t1, t2 = math.acos(xh), math.acos(xl)          # theta decreases with x
+    if t2 <= t1:
+        return 0.0
+    npan = max(8, int(math.ceil(2 * M * (t2 - t1) / math.pi)))
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    edges = np.linspace(t1, t2, npan + 1)
+    h = 0.5 * (edges[1:] - edges[:-1])
+    th = ((edges[:-1] + edges[1:]) * 0.5)[:, None] + h[:, None] * xg[None, :]
+    w = h[:, None] * wg[None, :]
+    m = np.arange(1, M)
+    f = g[0] * mu[0] + 2.0 * (g[1:] * mu[1:] * np.cos(th[..., None] * m)).sum(-1)
+    return float(D * (f * w).sum() / np.pi)
+
+
+def dos_margin(mu, D, a, b, lo, hi, n_s, iters=60):
+    """Eq. DOS:search: the smallest margin delta' >= 0 such that the search
+    interval [lo - delta', hi + delta'] holds n_s states by the KPM count,
+    found by bisection on [0, (b - a)/2] (returns (b - a)/2 when even that
+    holds fewer)."""
+    S = 0.5 * (b - a)
+    if dos_count(mu, D, a, b, lo - S, hi + S) < n_s:
+        return S
+    l, r = 0.0, S
+    for _ in range(iters):
+        mid = 0.5 * (l + r)
+        if dos_count(mu, D, a, b, lo - mid, hi + mid) >= n_s:
+            r = mid
+        else:
+            l = mid
+    return r
 
 
 # closed-form models ----------------------------------------------------------

@@ -259,38 +259,6 @@ double orc_poly_eval(const double *gamma, int n_p, double a, double b, double la
     return s;
 }
 
-/* Damping factor sigma and quality eta of the filter (Sec. 2.3):
- *   sigma = max_{x in [a,b] \ I_S} |p(x)| / min_{x in I_T} |p(x)|,
- *   eta = -N_p / log10(sigma).
- * The extrema are taken over a uniform grid in theta = acos(x) with
- * `pts_per_period` points per period 2*pi/N_p of T_{N_p}, plus the interval
- * edges.  Returns sigma; *eta receives eta (inf when sigma >= 1). */
-double orc_filter_quality(const double *gamma, int n_p, double a, double b,
-                          double t_lo, double t_hi, double s_lo, double s_hi,
-                          int pts_per_period, double *eta)
-{
-    int64_t npts = (int64_t)pts_per_period * (n_p + 1) / 2 + 16;
-    double mx = 0.0, mn = INFINITY;
-#pragma omp parallel for schedule(static) reduction(max:mx) reduction(min:mn)
-    for (int64_t k = 0; k <= npts; ++k) {
-        double th = M_PI * (double)k / (double)npts;
-        double lam = a + (b - a) * 0.5 * (cos(th) + 1.0);
-        double p = fabs(orc_poly_eval(gamma, n_p, a, b, lam));
-        if (lam >= t_lo && lam <= t_hi) { if (p < mn) mn = p; }
-        if (lam < s_lo || lam > s_hi) { if (p > mx) mx = p; }
-    }
-    double edges_in[2] = {t_lo, t_hi}, edges_out[2] = {s_lo, s_hi};
-    for (int e = 0; e < 2; ++e) {
-        double p = fabs(orc_poly_eval(gamma, n_p, a, b, edges_in[e]));
-        if (p < mn) mn = p;
-        p = fabs(orc_poly_eval(gamma, n_p, a, b, edges_out[e]));
-        if (p > mx) mx = p;
-    }
-    double sigma = mx / mn;
-    *eta = (sigma < 1.0) ? -n_p / log10(sigma) : INFINITY;
-    return sigma;
-}
-
 /* ------------------------------------------------------------------------ */
 /* Polynomial filter, Sec. 3.1 step 5 and Fig. fig:ChebFD.                   */
 /* X <- p(H) X with p(x) = sum_{n=0}^{n_p} gamma_n T_n(alpha x + beta),       */
@@ -588,14 +556,14 @@ void orc_rayleigh_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, con
 /* Readings where the paper leaves a choice:                                 */
 /*  - a Ritz pair with value in [lam_lo, lam_hi] is converged if r <= eps,   */
 /*    converging if eps < r <= sqrt(eps), a ghost candidate otherwise       */
-/*    (step 7);                                                             */
-/*  - exit (step 8) once, after at least two iterations, no in-window pair  */
-/*    is converging, the converged count equals that of the previous        */
-/*    iteration, and the smallest residual among the remaining in-window    */
-/*    pairs fell by less than 10% while none has converged, or by less     */
-/*    than half once some have (those pairs are ghosts: a large residual    */
-/*    that does not decrease; before the first convergence a slowly         */
-/*    converging search space still gains more than 10% per iteration);     */
+/*    (step 7 remarks: pairs whose residual stays above sqrt(eps) are       */
+/*    discarded as ghosts);                                                 */
+/*  - exit (step 8a, with those ghosts discarded) once, after at least two  */
+/*    iterations, no in-window pair is converging, the converged count      */
+/*    equals that of the previous iteration, and the ghost candidates       */
+/*    "remain" large: the smallest of their residuals did not decrease      */
+/*    from the previous iteration (a ghost's residual is large and does     */
+/*    not decrease, step 7 remarks).  No tolerance factor is applied;       */
 /*  - the restart block is the full set of n_s Ritz vectors (step 8b).      */
 /* Outputs the converged in-window pairs in ascending order.                 */
 /* ------------------------------------------------------------------------ */
@@ -644,7 +612,7 @@ int orc_chebfd_solve(int64_t n, const int64_t *rowptr, const int32_t *col, const
                 if (res[k] < rmin) rmin = res[k];
             }
         }
-        int stagnant = (rmin == INFINITY) || (rmin >= (nconv > 0 ? 0.5 : 0.9) * prev_rmin);
+        int stagnant = (rmin == INFINITY) || (rmin >= prev_rmin);
         if (it >= 2 && nconving == 0 && nconv == prev_conv && stagnant) { status = 0; break; }
         prev_conv = nconv;
         prev_rmin = rmin;

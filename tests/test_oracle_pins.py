@@ -225,7 +225,38 @@ def test_ti_kramers_pairs_and_gershgorin(orc):
     assert np.abs(w[0::2] - w[1::2]).max() < 1e-12        # Theta^2 = -1
     a, b = orc.gershgorin(H)
     assert a <= w[0] and w[-1] <= b
-    assert b == pytest.approx(8.5, abs=0.5) and a == pytest.approx(-8.5, abs=0.5)
+
+
+@pytest.mark.parametrize("L,pbc,V,seed", [((4, 4, 4), 3, 1.0, 3), ((5, 4, 3), 3, 1.7, 9),
+                                          ((3, 6, 2), 7, 0.4, 2)])
+def test_ti_gershgorin_exact(orc, L, pbc, V, seed):
+    """Gershgorin interval of Eq. (Ham) in closed form: row (n, o) has the
+    diagonal m g0(o) + V_n (g0 = +1 for tau = 0, -1 for tau = 1) and, per
+    existing neighbour along j, two off-diagonal entries of modulus t/2 (one
+    from G0, one from Gj), so its radius is t times the number of existing
+    neighbours: 2 per periodic direction of extent >= 3, and along an open
+    direction 2 in the interior, 1 on a surface.  A periodic direction of
+    extent 2 reaches the same site both ways: the two blocks add to -t G0
+    (the Gj parts cancel), one entry of modulus t.  V_n = V (u_n - 1/2) with
+    u_n the (separately pinned) counter hash of stream 0 at index n."""
+    m, t = 2.0, 1.0
+    H = orc.ti_hamiltonian(*L, pbc=pbc, t=t, m=m, V=V, seed=seed)
+    lo, hi = math.inf, -math.inf
+    for z in range(L[2]):
+        for y in range(L[1]):
+            for x in range(L[0]):
+                n = x + L[0] * (y + L[1] * z)
+                vn = V * (orc.u01(seed, 0, n) - 0.5)
+                nb = 0
+                for j, c in enumerate((x, y, z)):
+                    if (pbc >> j) & 1:
+                        nb += 2 if L[j] >= 3 else 1
+                    else:
+                        nb += (c > 0) + (c < L[j] - 1)
+                lo = min(lo, -m + vn - t * nb)
+                hi = max(hi, m + vn + t * nb)
+    a, b = orc.gershgorin(H)
+    assert a == pytest.approx(lo, abs=1e-14) and b == pytest.approx(hi, abs=1e-14)
 
 
 def test_ti_gauge_sign_of_hopping(orc):
@@ -243,3 +274,69 @@ def test_ti_small_periodic_duplicates_merge(orc):
     H = orc.ti_hamiltonian(2, 2, 2, pbc=7, V=0.0)
     w = np.linalg.eigvalsh(H.dense())
     assert np.abs(w - _periodic_spectrum((2, 2, 2))).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# filter quality (Sec. 2.3) in closed form
+# --------------------------------------------------------------------------
+def test_filter_quality_closed_forms(orc):
+    """sigma = max |p| outside I_S / min |p| inside I_T on [a, b] = [-1, 1]:
+    p = T_2 = 2x^2 - 1 with I_T = [-0.1, 0.1] has its smallest modulus
+    0.98 at the target edges and modulus 1 at x = +-1, so sigma = 1/0.98 > 1
+    (eta = inf); p = 1 - x^2 = (T_0 - T_2)/2 with I_S = [-0.5, 0.5] has 0.99
+    inside and at most 0.75 outside (at the search edges), sigma = 0.75/0.99
+    and eta = -2/log10(sigma);
+    p = x^2 = (T_0 + T_2)/2 with I_T = [0.4, 0.6], I_S = [0.3, 0.7] gives
+    0.16 inside and 1 at x = +-1 outside, sigma = 6.25 > 1 and eta = inf;
+    p = T_3 = 4x^3 - 3x with I_T = [0.5, 0.6], I_S = [0.2, 0.8]: inside,
+    T_3 rises from -1 at 0.5 towards its zero at sqrt(3)/2, so the smallest
+    modulus is |T_3(0.6)| = 0.936; outside the largest modulus is 1 (x = +-1),
+    sigma = 1/0.936.
+    The second case scaled to [a, b] = [-3, 5] (lambda = 1 + 4x) is the
+    same."""
+    s, e = orc.filter_quality([0.0, 0.0, 1.0], -1, 1, -0.1, 0.1, -0.5, 0.5)
+    assert s == pytest.approx(1 / 0.98, rel=1e-14) and e == math.inf
+    s, e = orc.filter_quality([0.5, 0.0, -0.5], -1, 1, -0.1, 0.1, -0.5, 0.5)
+    assert s == pytest.approx(0.75 / 0.99, rel=1e-14)
+    assert e == pytest.approx(-2 / math.log10(0.75 / 0.99), rel=1e-12)
+    s, e = orc.filter_quality([0.5, 0.0, 0.5], -1, 1, 0.4, 0.6, 0.3, 0.7)
+    assert s == pytest.approx(6.25, rel=1e-14) and e == math.inf
+    s, e = orc.filter_quality([0.0, 0.0, 0.0, 1.0], -1, 1, 0.5, 0.6, 0.2, 0.8)
+    assert s == pytest.approx(1 / 0.936, rel=1e-13)
+    s, e = orc.filter_quality([0.5, 0.0, 0.5], -3, 5, 2.6, 3.4, 2.2, 3.8)
+    assert s == pytest.approx(6.25, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# density of states from moments (Eq. DOS:target, Eq. DOS:search)
+# --------------------------------------------------------------------------
+def _exact_moments(lam, M, a, b):
+    x = (2 * lam - a - b) / (b - a)
+    return np.cos(np.outer(np.arange(M), np.arccos(x))).mean(1)
+
+
+@pytest.mark.parametrize("spectrum", ["flat", "linear"])
+def test_dos_count_and_margin_closed_forms(orc, spectrum):
+    """Exact moments mu_m = (1/D) sum_i T_m(x_i) of a known spectrum: the
+    KPM count of Eq. DOS:target over a window whose edges lie between
+    eigenvalues is the true count within 1 (the kernel smears each edge
+    symmetrically; 2048 moments resolve ~0.003, finer than the window); and
+    the margin of Eq. DOS:search for N_S = 2 N_T is delta' = delta for a
+    flat DOS (the search interval doubles) and (sqrt 2 - 1) delta for a DOS
+    proportional to |lambda| (the count grows as the square of the
+    half-width), within the KPM resolution."""
+    D = 4000
+    lam = inp.flat_spectrum(D) if spectrum == "flat" else inp.linear_spectrum(D)
+    a, b = -1.05, 1.05
+    mu = _exact_moments(lam, 2048, a, b)
+    d = 0.25
+    true = int((np.abs(lam) <= d).sum())
+    nt = orc.dos_count(mu, D, a, b, -d, d)
+    assert abs(nt - true) <= 1.0
+    dp = orc.dos_margin(mu, D, a, b, -d, d, 2 * true)
+    want = d if spectrum == "flat" else (math.sqrt(2) - 1) * d
+    assert abs(dp - want) <= 4 * (b - a) / 2048
+    # integrating the density itself gives the same count
+    xs = np.linspace(-d, d, 20001)
+    rho = orc.kpm_density(mu, a, b, xs)
+    assert D * integrate.simpson(rho, x=xs) == pytest.approx(nt, rel=1e-4)
