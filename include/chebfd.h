@@ -175,6 +175,22 @@ int chebfd_filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
                         const double *gamma, int n_p, double a, double b, void *X, void *U,
                         void *W, int64_t n_s, int64_t ld, double *moments_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as chebfd_filter_apply, same arguments and results (the same
+ * kernels in the same order, so bitwise equal output), but it allocates
+ * nothing.  With moments_dev != NULL the moment partial sums live in a fixed
+ * 64 MiB device array that the library holds on every GPU it runs on until
+ * the process ends (located by chebfd_create); the partials need
+ * 24 * n_s * (row blocks of one launch) bytes, e.g. 12.6 MB for 8 columns of
+ * a 524,288-row SELL-32 matrix.  Calls on one GPU share that array: calls
+ * that overlap in time on one GPU (two streams, two threads) race and give
+ * wrong moments.  Errors: as chebfd_filter_apply, and INVALID_ARG when the
+ * partial sums exceed the array. */
+int chebfd_filter_apply_noalloc(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                                const double *gamma, int n_p, double a, double b, void *X,
+                                void *U, void *W, int64_t n_s, int64_t ld, double *moments_dev);
+
 /* Y = (s_h H + s_u) X for a block (the plain spMMVM, Sec. 4), same layout
  * rules as chebfd_filter_apply; X and Y must not overlap. */
 int chebfd_spmm(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, const void *X, void *Y,

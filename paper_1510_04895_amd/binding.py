@@ -76,6 +76,8 @@ def lib():
         "chebfd_filter_quality": (i32, [vp, i32, dbl, dbl, dbl, dbl, dbl, dbl, vp, vp]),
         "chebfd_optimal_np": (i32, [dbl, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "chebfd_filter_apply": (i32, [vp, vp, i32, vp, i32, dbl, dbl, vp, vp, vp, i64, i64, vp]),
+        "chebfd_filter_apply_noalloc": (i32, [vp, vp, i32, vp, i32, dbl, dbl, vp, vp, vp, i64,
+                                              i64, vp]),
         "chebfd_lanczos_bounds": (i32, [vp, vp, i32, u64, dbl, vp, vp]),
         "chebfd_spmm": (i32, [vp, vp, i32, vp, vp, i64, i64, dbl, dbl]),
         "chebfd_gram": (i32, [vp, i32, vp, i64, i64, vp, i64, i64, i64, vp]),
@@ -121,7 +123,8 @@ def exported_symbols():
     return [n for n in ("chebfd_create chebfd_destroy chebfd_synchronize chebfd_strerror "
                         "chebfd_last_error chebfd_version chebfd_matrix_from_csr chebfd_matrix_ti "
                         "chebfd_matrix_info chebfd_matrix_destroy chebfd_coeffs "
-                        "chebfd_filter_quality chebfd_optimal_np chebfd_filter_apply chebfd_spmm "
+                        "chebfd_filter_quality chebfd_optimal_np chebfd_filter_apply "
+                        "chebfd_filter_apply_noalloc chebfd_spmm "
                         "chebfd_lanczos_bounds "
                         "chebfd_gram chebfd_block_times chebfd_residual_norms "
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
@@ -284,6 +287,14 @@ def chebfd_filter_apply(ctx, H, gamma, a, b, X, U, W, moments=None, n_s=None):
     n_s = X.shape[1] if n_s is None else n_s
     _check(lib().chebfd_filter_apply(ctx.h, H.h, _prec(X), _ptr(g), g.size - 1, a, b, _ptr(X),
                                      _ptr(U), _ptr(W), n_s, _ld(X), _ptr(moments)))
+
+
+def chebfd_filter_apply_noalloc(ctx, H, gamma, a, b, X, U, W, moments=None, n_s=None):
+    g = _dbl(gamma)
+    n_s = X.shape[1] if n_s is None else n_s
+    _check(lib().chebfd_filter_apply_noalloc(ctx.h, H.h, _prec(X), _ptr(g), g.size - 1, a, b,
+                                             _ptr(X), _ptr(U), _ptr(W), n_s, _ld(X),
+                                             _ptr(moments)))
 
 
 def chebfd_spmm(ctx, H, X, Y, s_h=1.0, s_u=0.0):

@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libchebfd.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["capi.cpp", "matrix.cpp", "host_poly.cpp", "host_eig.cpp", "solver.cpp", "learned.cpp", "lanczos.cpp",
-           "kernels_step.hip", "kernels_stencil.hip", "kernels_dense.hip", "kernels_mlp.hip"]
+           "kernels_step.hip", "kernels_stencil.hip", "kernels_dense.hip", "kernels_mlp.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -89,18 +89,45 @@ int check_block(const char *who, int precision, const void *p, int64_t n, int64_
     return CHEBFD_OK;
 }
 
+size_t moment_partial_bytes(const chebfd_ctx *ctx, const chebfd_matrix *H, int prec, int64_t n_s)
+{
+    return (size_t)step_partial_blocks(ctx, H, prec, n_s) * (size_t)n_s * 3 * sizeof(double);
+}
+
+// Argument checks of chebfd_filter_apply (shared with its allocation-free
+// variant).
+int check_filter_args(const char *who, chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                      const double *gamma, int n_p, double a, double b, void *X, void *U,
+                      void *W, int64_t n_s, int64_t ld)
+{
+    if (!ctx || !H || !gamma) return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": NULL argument");
+    if (n_p < 2) return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": n_p must be >= 2");
+    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b))
+        return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": need finite a < b");
+    int rc;
+    if ((rc = check_block(who, precision, X, H->n, n_s, ld, true)) ||
+        (rc = check_block(who, precision, U, H->n, n_s, ld, true)) ||
+        (rc = check_block(who, precision, W, H->n, n_s, ld, true)))
+        return rc;
+    if (X == U || X == W || U == W)
+        return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": X, U, W must be distinct");
+    for (int k = 0; k <= n_p; ++k)
+        if (!std::isfinite(gamma[k]))
+            return fail(CHEBFD_ERR_NONFINITE, std::string(who) + ": non-finite coefficient");
+    return CHEBFD_OK;
+}
+
 // The polynomial filter (Fig. fig:ChebFD) on caller buffers.
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom, int progress)
+                 double *mom, int progress, double *partials)
 {
     const double alpha = 2.0 / (b - a), beta = (a + b) / (a - b);
-    double *part = nullptr;
+    double *part = partials;
     int64_t n_part = 0;
-    if (mom) {
+    if (mom && !part) {
         // partial sums: one row of 3 per column per workgroup row block
-        const int64_t nparts = step_partial_blocks(ctx, H, prec, n_s);
-        int rc = ensure_scratch(ctx, (size_t)nparts * n_s * 3 * sizeof(double));
+        int rc = ensure_scratch(ctx, moment_partial_bytes(ctx, H, prec, n_s));
         if (rc) return rc;
         part = (double *)ctx->scratch;
     }
@@ -192,6 +219,8 @@ int chebfd_create(chebfd_ctx **out, int device, void *hip_stream)
     if (device < 0 || device >= count)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_create: device index out of range");
     CHEBFD_HIP(hipSetDevice(device));
+    // the allocation-free entry point's device array, located once per device
+    if (int rc = noalloc_setup(device)) return rc;
     auto *c = new chebfd_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -223,20 +252,9 @@ int chebfd_filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
                         const double *gamma, int n_p, double a, double b, void *X, void *U,
                         void *W, int64_t n_s, int64_t ld, double *moments_dev)
 {
-    if (!ctx || !H || !gamma) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_filter_apply: NULL argument");
-    if (n_p < 2) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_filter_apply: n_p must be >= 2");
-    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b))
-        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_filter_apply: need finite a < b");
-    int rc;
-    if ((rc = check_block("chebfd_filter_apply", precision, X, H->n, n_s, ld, true)) ||
-        (rc = check_block("chebfd_filter_apply", precision, U, H->n, n_s, ld, true)) ||
-        (rc = check_block("chebfd_filter_apply", precision, W, H->n, n_s, ld, true)))
-        return rc;
-    if (X == U || X == W || U == W)
-        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_filter_apply: X, U, W must be distinct");
-    for (int k = 0; k <= n_p; ++k)
-        if (!std::isfinite(gamma[k]))
-            return fail(CHEBFD_ERR_NONFINITE, "chebfd_filter_apply: non-finite coefficient");
+    int rc = check_filter_args("chebfd_filter_apply", ctx, H, precision, gamma, n_p, a, b, X, U,
+                               W, n_s, ld);
+    if (rc) return rc;
     CHEBFD_HIP(hipSetDevice(ctx->device));
     return filter_apply(ctx, H, precision, gamma, n_p, a, b, X, U, W, n_s, ld, moments_dev);
 }

@@ -146,9 +146,19 @@ int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, 
 int launch_expand_T(chebfd_ctx *ctx, const double *T, int64_t k, int64_t m, double *Tr);
 int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, void *dst,
                        int64_t ldd, int64_t d0, const int32_t *idx_dev, int64_t n, int64_t m);
+// The filter of Fig. fig:ChebFD; with mom != nullptr the moment partial sums
+// go to `partials` (moment_partial_bytes long) or, if that is nullptr, to the
+// context's grow-only scratch.
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom, int progress = 0);
+                 double *mom, int progress = 0, double *partials = nullptr);
+size_t moment_partial_bytes(const chebfd_ctx *ctx, const chebfd_matrix *H, int prec, int64_t n_s);
+int check_filter_args(const char *who, chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                      const double *gamma, int n_p, double a, double b, void *X, void *U,
+                      void *W, int64_t n_s, int64_t ld);
+// Locates the allocation-free entry point's device array on `device` (the
+// current device); called once per device by chebfd_create.
+int noalloc_setup(int device);
 int check_block(const char *who, int precision, const void *p, int64_t n, int64_t n_s,
                 int64_t ld, bool packed);
 // Lanczos spectral bounds (lanczos.cpp); V3 = n x 3 c128 scratch (ld 3),
