@@ -361,22 +361,53 @@ void orc_moments_direct(int64_t n, const int64_t *rowptr, const int32_t *col, co
 /* ------------------------------------------------------------------------ */
 
 /* S = A^H B (n_a x n_b) with Kahan-compensated sums over the n rows
- * (Sec. 3.1, step 6 remarks). A: n x n_a, B: n x n_b, row-major. */
+ * (Sec. 3.1, step 6 remarks). A: n x n_a, B: n x n_b, row-major.
+ * The paper fixes the compensation, not the association of the sums: the
+ * rows are split into one contiguous range per thread, each range is summed
+ * in row order with compensation (s - c is the range sum), and the range
+ * sums are then added in range order, again with compensation.  Each thread
+ * reads every row of its range once (row-major blocks). */
 void orc_gram_kahan(int64_t n, const cplx *A, int64_t n_a, const cplx *B, int64_t n_b, cplx *S)
 {
-#pragma omp parallel for schedule(static) collapse(2)
-    for (int64_t k = 0; k < n_a; ++k)
-        for (int64_t l = 0; l < n_b; ++l) {
-            double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-            for (int64_t i = 0; i < n; ++i) {
-                cplx p = conj(A[i * n_a + k]) * B[i * n_b + l];
-                double y = creal(p) - cr, t = sr + y;
-                cr = (t - sr) - y; sr = t;
-                y = cimag(p) - ci; t = si + y;
-                ci = (t - si) - y; si = t;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    const int64_t m = n_a * n_b;
+    double *acc = (double *)calloc((size_t)nt * (size_t)m * 4, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        const int64_t i0 = n * t / nt, i1 = n * (t + 1) / nt;
+        double *sr = acc + (size_t)t * m * 4, *cr = sr + m, *si = cr + m, *ci = si + m;
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t k = 0; k < n_a; ++k) {
+                const cplx a = conj(A[i * n_a + k]);
+                for (int64_t l = 0; l < n_b; ++l) {
+                    const cplx p = a * B[i * n_b + l];
+                    const int64_t q = k * n_b + l;
+                    double y = creal(p) - cr[q], tt = sr[q] + y;
+                    cr[q] = (tt - sr[q]) - y; sr[q] = tt;
+                    y = cimag(p) - ci[q]; tt = si[q] + y;
+                    ci[q] = (tt - si[q]) - y; si[q] = tt;
+                }
             }
-            S[k * n_b + l] = sr + I * si;
+    }
+    for (int64_t q = 0; q < m; ++q) {
+        double sre = 0.0, cre = 0.0, sim = 0.0, cim = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const double *sr = acc + (size_t)t * m * 4, *cr = sr + m, *si = cr + m, *ci = si + m;
+            double y = (sr[q] - cr[q]) - cre, tt = sre + y;
+            cre = (tt - sre) - y; sre = tt;
+            y = (si[q] - ci[q]) - cim; tt = sim + y;
+            cim = (tt - sim) - y; sim = tt;
         }
+        S[q] = sre + I * sim;
+    }
+    free(acc);
 }
 
 /* C = A T with A: n x k (row-major), T: k x m, C: n x m. */
@@ -540,6 +571,7 @@ void orc_rayleigh_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, con
     memcpy(Y, Tmp, sizeof(cplx) * (size_t)(n * n_s));
     orc_block_times_small(n, W, n_s, Uv, n_s, Tmp);
     memcpy(W, Tmp, sizeof(cplx) * (size_t)(n * n_s));
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < ns; ++k) {
         double s = 0.0;
         for (int64_t i = 0; i < n; ++i) {
