@@ -10,6 +10,7 @@
 // and the search interval follows from N_S = N int_{I_S} rho (Eq. DOS:search).
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -20,9 +21,13 @@ namespace {
 double window_count(const double *mu, int n_mom, int64_t n, double a, double b, double lo,
                     double hi)
 {
-    std::vector<double> c(n_mom), g(n_mom);
+    // damping() fills n + 1 factors for degree n.  Table tab:Kernel with
+    // N_p = n_mom is the Jackson kernel of n_mom - 1 moments: its factor
+    // g_{n_mom-1} (like g_{n_mom}) is zero, so moment n_mom - 1 carries no
+    // weight.
+    std::vector<double> c(n_mom), g(n_mom + 1);
     window_coeffs(lo, hi, a, b, n_mom - 1, c.data());
-    damping(CHEBFD_KERNEL_JACKSON, n_mom, 0.0, g.data());   // N = n_mom (KPM convention)
+    damping(CHEBFD_KERNEL_JACKSON, n_mom, 0.0, g.data());
     double s = 0.0;
     for (int m = 0; m < n_mom; ++m) s += g[m] * c[m] * mu[m];
     return (double)n * s;
@@ -255,5 +260,107 @@ extern "C" int chebfd_fit_corrections(double a, double b, double t_lo, double t_
         for (int j = 0; j < n_hat; ++j) pen += best[j] * best[j];
         *sigma_out = std::exp(best_L - l2 * pen);
     }
+    return CHEBFD_OK;
+}
+
+// The learned form end to end (KPM moments -> network -> decode -> gate).
+extern "C" int chebfd_learned_params(chebfd_ctx *ctx, const chebfd_matrix *H, chebfd_mlp *mlp,
+                                     double a, double b, double lam_lo, double lam_hi, int n_vec,
+                                     int n_mom, int n_mom_rule, uint64_t seed, double ns_over_nt,
+                                     int n_hat,
+                                     double c_max, int ns_max, int gate, int *n_p, int *n_s,
+                                     double *gamma_corr, int corr_cap, int *corr_kept,
+                                     int *np_rule, int *ns_rule)
+{
+    if (!ctx || !H || !mlp || !n_p || !n_s || !(a < b) || !(lam_lo < lam_hi) || n_vec < 1 ||
+        n_mom < 4 || n_hat < 2 || ns_max < 16 || (gamma_corr && corr_cap < 1))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_learned_params: invalid arguments");
+    int ni = 0, no = 0;
+    int rc = chebfd_mlp_dims(mlp, &ni, nullptr, &no);
+    if (rc) return rc;
+    if (ni != n_mom + 2 || no != 2 + n_hat)
+        return fail(CHEBFD_ERR_INVALID_ARG,
+                    "chebfd_learned_params: network needs n_mom + 2 inputs and 2 + n_hat outputs");
+    // stochastic KPM moments in complex64 (Sec. 3.1 step 1); the network
+    // reads the first n_mom, the rule all n_mom_rule of them (the moments of
+    // a longer expansion begin with those of the shorter one)
+    const int nm = std::max(n_mom, n_mom_rule + (n_mom_rule & 1));
+    std::vector<double> mu(nm);
+    if ((rc = chebfd_kpm_moments(ctx, H, CHEBFD_PREC_C64, n_vec + (n_vec & 1), nm, seed, a, b,
+                                 mu.data())))
+        return rc;
+    // the rule (fallback and reference of the network's ratios); a positive
+    // *n_s on entry fixes N_S
+    const int ns_fixed = *n_s > 0 ? *n_s : 0;
+    const int64_t n = H->n;
+    double nt = 0.0;
+    int ns0 = ns_fixed, np0 = 0;
+    const int ns_cap = std::max(ns_max, ns_fixed);
+    if ((rc = chebfd_dos_params(mu.data(), nm, n, a, b, lam_lo, lam_hi, ns_over_nt,
+                                CHEBFD_KERNEL_LANCZOS, 2.0, ns_cap, &nt, &ns0, &np0, nullptr)))
+        return rc;
+    if (np_rule) *np_rule = np0;
+    if (ns_rule) *ns_rule = ns0;
+    // network on the device
+    std::vector<float> feat(n_mom + 2), outv(no);
+    if ((rc = chebfd_learned_features(mu.data(), n_mom, a, b, lam_lo, lam_hi, feat.data())))
+        return rc;
+    float *dev = nullptr;
+    CHEBFD_HIP(hipMalloc((void **)&dev, (size_t)(ni + no) * sizeof(float)));
+    rc = CHEBFD_OK;
+    if (hipMemcpyAsync(dev, feat.data(), (size_t)ni * 4, hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess)
+        rc = fail(CHEBFD_ERR_HIP, "chebfd_learned_params: upload failed");
+    if (!rc) rc = chebfd_mlp_forward(ctx, mlp, dev, 1, dev + ni);
+    if (!rc && hipMemcpyAsync(outv.data(), dev + ni, (size_t)no * 4, hipMemcpyDeviceToHost,
+                              ctx->stream) != hipSuccess)
+        rc = fail(CHEBFD_ERR_HIP, "chebfd_learned_params: download failed");
+    if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = fail(CHEBFD_ERR_HIP, "chebfd_learned_params: synchronize failed");
+    (void)hipFree(dev);
+    if (rc) return rc;
+    // decode; the corrections are evaluated for n = 0..n_p
+    if (ns_fixed) outv[1] = 0.0f;
+    int npl = 0, nsl = 0;
+    if ((rc = chebfd_learned_decode(outv.data(), np0, ns0, n_hat, c_max, ns_cap, &npl, &nsl,
+                                    nullptr, 0)))
+        return rc;
+    *n_p = npl;
+    *n_s = nsl;
+    if (corr_kept) *corr_kept = 0;
+    if (!gamma_corr) return CHEBFD_OK;
+    if (npl + 1 > corr_cap)
+        return fail(CHEBFD_ERR_WORKSPACE,
+                    "chebfd_learned_params: gamma_corr needs n_p + 1 = " + std::to_string(npl + 1) +
+                        " entries");
+    std::vector<double> corr(npl + 1, 0.0);
+    if ((rc = chebfd_learned_decode(outv.data(), np0, ns0, n_hat, c_max, ns_cap, &npl, &nsl,
+                                    corr.data(), npl + 1)))
+        return rc;
+    bool keep = false;
+    for (double c : corr) keep = keep || c != 0.0;
+    if (keep && gate) {
+        // the plain expansion is the fallback: keep the corrections only if
+        // they lower the damping factor sigma (Sec. 2.3) of the filter for
+        // the rule's search interval at this (N_p, N_S)
+        double nt2 = 0.0, margin = 0.0;
+        int ns_fix = nsl, np_dummy = 0;
+        if ((rc = chebfd_dos_params(mu.data(), nm, n, a, b, lam_lo, lam_hi, ns_over_nt,
+                                    CHEBFD_KERNEL_LANCZOS, 2.0, std::max(ns_cap, nsl), &nt2,
+                                    &ns_fix, &np_dummy, &margin)))
+            return rc;
+        std::vector<double> g(npl + 1), gc(npl + 1);
+        if ((rc = chebfd_coeffs(lam_lo, lam_hi, a, b, npl, CHEBFD_KERNEL_LANCZOS, 2.0, g.data())))
+            return rc;
+        for (int k = 0; k <= npl; ++k) gc[k] = g[k] * (1.0 + corr[k]);
+        double s_plain, s_corr, e;
+        quality(g.data(), npl, a, b, lam_lo, lam_hi, lam_lo - margin, lam_hi + margin, &s_plain,
+                &e);
+        quality(gc.data(), npl, a, b, lam_lo, lam_hi, lam_lo - margin, lam_hi + margin, &s_corr,
+                &e);
+        keep = s_corr < s_plain;
+    }
+    for (int k = 0; k <= npl; ++k) gamma_corr[k] = keep ? corr[k] : 0.0;
+    if (corr_kept) *corr_kept = keep ? 1 : 0;
     return CHEBFD_OK;
 }

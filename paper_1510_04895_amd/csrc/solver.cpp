@@ -66,11 +66,13 @@ Layout layout(int64_t n, const chebfd_params &p)
     L.blk64 = align256((size_t)n * p.n_s * 16);
     L.blk32 = align256((size_t)n * p.n_s * 8);
     size_t off = 0;
-    // three c128 blocks (in the C64 form the first one also hosts the two
-    // c64 filter scratch blocks U32, W32)
+    // three c128 blocks; in the C64 form the first one also hosts the two
+    // c64 filter scratch blocks U32 (at 0) and W32 (at blk32), so it spans
+    // at least 2 blk32 bytes (align256 can make 2 blk32 exceed blk64)
     for (int i = 0; i < 3; ++i) {
         L.off_b[i] = off;
-        off += L.blk64;
+        off += (i == 0 && p.precision == CHEBFD_PREC_C64) ? std::max(L.blk64, 2 * L.blk32)
+                                                          : L.blk64;
     }
     if (p.precision == CHEBFD_PREC_C64) {
         L.off_x32 = off;
@@ -176,7 +178,13 @@ struct Solver {
             std::vector<double> d(k);
             for (int i = 0; i < k; ++i) {
                 const double s = S[2 * ((size_t)i * k + i)];
-                if (!std::isfinite(s)) return fail(CHEBFD_ERR_NONFINITE, "non-finite Gram diagonal");
+                if (!std::isfinite(s)) {
+                    // on an estimated interval the filter grows without
+                    // bound outside [a, b] (T_n(x) for |x| > 1): an overflow
+                    // proves the interval too narrow
+                    if (bounds_checked) return RESTART_WIDER;
+                    return fail(CHEBFD_ERR_NONFINITE, "non-finite Gram diagonal");
+                }
                 d[i] = s > 0.0 ? 1.0 / std::sqrt(s) : 0.0;
             }
             for (int i = 0; i < k; ++i)
@@ -199,7 +207,10 @@ struct Solver {
                 done = true;
             }
             if (!done) {
-                if (herm_eig(k, S, w) != 0) return fail(CHEBFD_ERR_NONFINITE, "SVQB eigensolver failed");
+                if (herm_eig(k, S, w) != 0) {
+                    if (bounds_checked) return RESTART_WIDER;
+                    return fail(CHEBFD_ERR_NONFINITE, "SVQB eigensolver failed");
+                }
                 const double tmax = w[k - 1];
                 // T = D U Theta^{-1/2}, kept directions, largest first
                 T.assign((size_t)2 * k * k, 0.0);
@@ -317,7 +328,10 @@ struct Solver {
             s.s_u = 0.0;
             if ((rc = launch_step(ctx, H, s, nullptr))) return rc;        // U = H X
             if ((rc = gram_host(CHEBFD_PREC_C128, X, k, CHEBFD_PREC_C128, U, k, S))) return rc;
-            if (herm_eig(k, S, theta) != 0) return fail(CHEBFD_ERR_NONFINITE, "Rayleigh-Ritz eigensolver failed");
+            if (herm_eig(k, S, theta) != 0) {
+                if (bounds_checked) return RESTART_WIDER;
+                return fail(CHEBFD_ERR_NONFINITE, "Rayleigh-Ritz eigensolver failed");
+            }
             if ((rc = upload_T(S, k, k))) return rc;
             // W = X Ug (Ritz vectors), X = U Ug (H times Ritz vectors)
             if ((rc = launch_block_times(ctx, CHEBFD_PREC_C128, X, ns, n, k, dTr, k, CHEBFD_PREC_C128, W, ns, 0)))
