@@ -358,6 +358,8 @@ int chebfd_mlp_create(chebfd_ctx *ctx, int n_in, int n_hidden, int n_out, uint64
                       chebfd_mlp **out);
 int chebfd_mlp_destroy(chebfd_mlp *mlp);
 int chebfd_mlp_num_params(const chebfd_mlp *mlp, int64_t *n);
+/* Layer widths of a network (host outputs, any may be NULL). */
+int chebfd_mlp_dims(const chebfd_mlp *mlp, int *n_in, int *n_hidden, int *n_out);
 /* Copies parameters / output shift and scale (n_out each) to or from the host;
  * any pointer may be NULL.  Synchronises. */
 int chebfd_mlp_get_params(chebfd_ctx *ctx, const chebfd_mlp *mlp, float *params, float *shift,
@@ -383,6 +385,39 @@ int chebfd_mlp_loss_grad(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *X_dev,
 int chebfd_mlp_train_step(chebfd_ctx *ctx, chebfd_mlp *mlp, const float *X_dev,
                           const float *T_dev, int batch, float lr, float weight_decay,
                           float *loss);
+
+/* The learned parameter choice for the window [lam_lo, lam_hi] of H in
+ * the spectral interval [a, b], end to end on the device and the host
+ * (Sec. 3.1 steps 1-3 with the network in place of the rule):
+ *   1. max(n_mom, n_mom_rule) stochastic KPM moments from n_vec
+ *      random-phase vectors (chebfd_kpm_moments, complex64, stream 2 of
+ *      `seed`; n_vec rounded up to even);
+ *   2. the rule-based choice from all of them (chebfd_dos_params with
+ *      ns_over_nt, Lanczos kernel mu = 2, ns_max), returned in *np_rule,
+ *      *ns_rule (may be NULL); a positive *n_s on entry fixes N_S (the rule
+ *      then gives N_p for it and the network's N_S output is ignored);
+ *   3. the network `mlp` (n_mom + 2 inputs from chebfd_learned_features
+ *      on the first n_mom moments, 2 + n_hat outputs) on the context's
+ *      stream;
+ *   4. chebfd_learned_decode into *n_p, *n_s and the corrections corr_n,
+ *      n = 0..n_p (amplitude c_max);
+ *   5. with gate != 0 the corrections are kept only if they lower the
+ *      damping factor sigma (Sec. 2.3) of the Lanczos-kernel filter of
+ *      degree *n_p for the search interval the rule gives at *n_s; else (or
+ *      for a zero network output) gamma_corr is all zero, which is exactly
+ *      the plain method (the fallback).  *corr_kept (may be NULL) says which.
+ * gamma_corr (host, may be NULL) receives *n_p + 1 doubles, to pass as
+ * chebfd_params.gamma_corr; if corr_cap < *n_p + 1 the call returns
+ * CHEBFD_ERR_WORKSPACE with *n_p and *n_s already set.  Allocates a few
+ * hundred bytes of device memory and the moment blocks (3 N n_vec complex64)
+ * for the call.  Synchronises.  Errors: INVALID_ARG (network shape, sizes),
+ * WORKSPACE, HIP. */
+int chebfd_learned_params(chebfd_ctx *ctx, const chebfd_matrix *H, chebfd_mlp *mlp, double a,
+                          double b, double lam_lo, double lam_hi, int n_vec, int n_mom,
+                          int n_mom_rule, uint64_t seed, double ns_over_nt, int n_hat,
+                          double c_max, int ns_max,
+                          int gate, int *n_p, int *n_s, double *gamma_corr, int corr_cap,
+                          int *corr_kept, int *np_rule, int *ns_rule);
 
 /* ------------------------------------------------------------------ */
 /* the ChebFD solver (Sec. 3.1 steps 1-8)                              */

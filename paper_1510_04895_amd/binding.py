@@ -98,6 +98,9 @@ def lib():
         "chebfd_mlp_create": (i32, [vp, i32, i32, i32, u64, pp]),
         "chebfd_mlp_destroy": (i32, [vp]),
         "chebfd_mlp_num_params": (i32, [vp, vp]),
+        "chebfd_mlp_dims": (i32, [vp, vp, vp, vp]),
+        "chebfd_learned_params": (i32, [vp, vp, vp, dbl, dbl, dbl, dbl, i32, i32, i32, u64, dbl,
+                                        i32, dbl, i32, i32, vp, vp, vp, i32, vp, vp, vp]),
         "chebfd_mlp_get_params": (i32, [vp, vp, vp, vp, vp]),
         "chebfd_mlp_set_params": (i32, [vp, vp, vp, vp, vp]),
         "chebfd_mlp_forward": (i32, [vp, vp, vp, i32, vp]),
@@ -134,7 +137,8 @@ def exported_symbols():
                         "chebfd_learned_decode chebfd_fit_corrections chebfd_mlp_create "
                         "chebfd_mlp_destroy chebfd_mlp_num_params chebfd_mlp_get_params "
                         "chebfd_mlp_set_params chebfd_mlp_forward chebfd_mlp_loss_grad "
-                        "chebfd_mlp_train_step chebfd_mlp_input_scaling").split()]
+                        "chebfd_mlp_train_step chebfd_mlp_input_scaling chebfd_mlp_dims "
+                        "chebfd_learned_params").split()]
 
 
 def _check(rc, allow_warn=False):
@@ -465,6 +469,30 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def chebfd_learned_params(ctx, H, mlp, a, b, lam_lo, lam_hi, n_vec=8, n_mom=256, n_mom_rule=0,
+                          seed=1, ns_over_nt=3.0, n_hat=64, c_max=0.5, ns_max=256, gate=True,
+                          n_s=0):
+    """(n_p, n_s, corrections or None, rule (n_p, n_s)) from the library's
+    learned-form entry point (argument marshalling only)."""
+    n_p, kept, npr, nsr = (C.c_int() for _ in range(4))
+    cap = 4096
+    while True:
+        corr = np.zeros(cap)
+        ns_ = C.c_int(n_s)
+        rc = lib().chebfd_learned_params(ctx.h, H.h, mlp.h_, a, b, lam_lo, lam_hi, n_vec, n_mom,
+                                         n_mom_rule, seed, ns_over_nt, n_hat, c_max, ns_max,
+                                         int(gate),
+                                         C.byref(n_p), C.byref(ns_), _ptr(corr), cap,
+                                         C.byref(kept), C.byref(npr), C.byref(nsr))
+        if rc == -6 and n_p.value + 1 > cap:
+            cap = n_p.value + 1
+            continue
+        _check(rc)
+        break
+    c = corr[:n_p.value + 1].copy() if kept.value else None
+    return n_p.value, ns_.value, c, (npr.value, nsr.value)
 
 
 def default_params(**kw):

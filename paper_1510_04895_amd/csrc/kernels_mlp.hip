@@ -292,6 +292,15 @@ int chebfd_mlp_destroy(chebfd_mlp *M)
     return CHEBFD_OK;
 }
 
+int chebfd_mlp_dims(const chebfd_mlp *M, int *n_in, int *n_hidden, int *n_out)
+{
+    if (!M) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_mlp_dims: NULL network");
+    if (n_in) *n_in = M->n_in;
+    if (n_hidden) *n_hidden = M->h;
+    if (n_out) *n_out = M->n_out;
+    return CHEBFD_OK;
+}
+
 int chebfd_mlp_num_params(const chebfd_mlp *M, int64_t *n)
 {
     if (!M || !n) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_mlp_num_params: NULL argument");
