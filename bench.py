@@ -137,9 +137,9 @@ def main():
                     help="skip the extra solve on Lanczos bounds")
     ap.add_argument("--no-other-storage", action="store_true",
                     help="skip the fused-kernel timing (and solve) of the other storage")
-    ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1, 2],
+    ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1],
                     help="block order of the fused step (tuning key 'order'): -1 automatic, "
-                         "0 column-slab major, 1 row-chunk major, 2 lattice z-march")
+                         "0 column-slab major, 1 tiled lattice order (matrix-free lattice)")
     ap.add_argument("--kernel-steps", type=int, default=100,
                     help="fused launches timed with HIP events for the roofline figure")
     args = ap.parse_args()

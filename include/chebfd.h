@@ -242,35 +242,28 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *   "lanes"       lanes sharing one row (SELL) or site (stencil): 16, 32, 64,
  *                 0 = default (32; 16 for blocks of at most 16 packs);
  *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
- *   "order"       -1 (default) = automatic: the matrix-free lattice runs
- *                 the z-march when, column-slab major, the bytes moved
- *                 between a site's gather as a z-neighbour from above and
- *                 from below (two lattice planes of the five block streams
- *                 over one slab) exceed the 256 MB memory-side cache, and
- *                 is column-slab major otherwise; SELL is column-slab major;
- *                 0 = workgroups ordered column-slab major,
- *                 1 = row-chunk major, 2 = lattice z-march (matrices from
- *                 chebfd_matrix_ti: blocks of one z-column run consecutively
- *                 on one XCD; other matrices fall back to 0);
- *   "gathers"     SELL only: gathered rows in flight per row, 8 or 16 (default);
- *   "pipeline"    SELL only: 0 (default) = one row block per workgroup,
- *                 1 = persistent workgroups that stage the next row block
- *                 while the current one is gathered;
- *   "slab_group"  SELL only: column slabs taken G at a time with the G slabs
- *                 of a row block back to back (one staging from memory per
- *                 group); a power of two, 0 (default) = from "order";
+ *   "order"       matrix-free lattice only: -1 (default) = automatic: the
+ *                 tiled lattice order when, column-slab major, the bytes
+ *                 moved between a site's gather as a z-neighbour from above
+ *                 and from below (two lattice planes of the five block
+ *                 streams over one slab) exceed the 256 MB memory-side
+ *                 cache, column-slab major otherwise; 0 = column-slab major
+ *                 with sites in lattice order; 1 = tiled lattice order
+ *                 (strips of "tile" x-columns, z fastest inside a column,
+ *                 one strip per XCD group);
+ *   "tile"        strip width of the tiled lattice order, in sites along x:
+ *                 -1 (default) = 4, used where the tiled order pays (above);
+ *                 a positive value also makes every SELL matrix built by
+ *                 chebfd_matrix_ti on this context take the tiled row order
+ *                 (the chunk composition of SELL-C-sigma); 0 = never tiled;
  *   "pair_rows"   SELL matrices built on this context: 1 (default) = inside
  *                 each chunk, rows whose entries gather the same columns at
  *                 the same positions are placed in adjacent slots (one wave
  *                 instruction), 0 = length-sorted order only;
- *   "waves"       SELL only: register budget of the staged kernel for 5
- *                 (default) or 4 resident waves per SIMD;
- *   "batches"     stencil only: the six neighbour sites requested in 1
- *                 (default) or 2 batches (in-plane, then z);
  *   "xcd_group"   consecutive workgroups placed on one of the 8 XCDs (each
  *                 with its own L2): 1 = hardware round-robin order, a power
- *                 of two up to 64, 0 = default (SELL: the workgroups of one
- *                 chunk; stencil: 1).
+ *                 of two up to 2^20, 0 = default (the workgroups of one SELL
+ *                 chunk, or of one strip in a tiled order; stencil otherwise 1).
  * The filtered blocks are bitwise identical for every setting (each element
  * is computed by the same operations in the same order); moment sums may
  * differ in rounding; only speed changes.

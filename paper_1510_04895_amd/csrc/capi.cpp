@@ -367,15 +367,10 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     const std::string k(key);
     if (k == "lanes" && (value == 0 || value == 16 || value == 32 || value == 64)) ctx->tune_lpr = value;
     else if (k == "nontemporal" && (value == 0 || value == 1)) ctx->tune_nt = value;
-    else if (k == "order" && value >= -1 && value <= 2) ctx->tune_order = value;
-    else if (k == "gathers" && (value == 8 || value == 16)) ctx->tune_gathers = value;
-    else if (k == "pipeline" && (value == 0 || value == 1)) ctx->tune_pipeline = value;
-    else if (k == "batches" && (value == 1 || value == 2)) ctx->tune_batches = value;
-    else if (k == "waves" && (value == 4 || value == 5)) ctx->tune_waves = value;
+    else if (k == "order" && value >= -1 && value <= 1) ctx->tune_order = value;
+    else if (k == "tile" && value >= -1 && value <= 256) ctx->tune_tile = value;
     else if (k == "pair_rows" && (value == 0 || value == 1)) ctx->tune_pair_rows = value;
-    else if (k == "slab_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
-        ctx->tune_slab_group = value;
-    else if (k == "xcd_group" && value >= 0 && value <= 64 && !(value & (value - 1)))
+    else if (k == "xcd_group" && value >= 0 && value <= (1 << 20) && !(value & (value - 1)))
         ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");
     return CHEBFD_OK;

@@ -33,4 +33,12 @@ inline int ilog2(int g)
     return l;
 }
 
+// the same for 64-bit counts
+inline int ilog2_64(int64_t g)
+{
+    int l = 0;
+    while (((int64_t)1 << (l + 1)) <= g) ++l;
+    return l;
+}
+
 }  // namespace chebfd

@@ -47,11 +47,9 @@ struct Sell {
     int32_t *col = nullptr;         // stored
     double *val64 = nullptr;        // stored complex128 (interleaved)
     float *val32 = nullptr;         // stored complex64
-    // optional traversal order of the chunks (a permutation; nullptr =
-    // natural order) and the number of consecutive scheduled chunks that
-    // form one locality group (a z-column of a lattice)
-    int32_t *sched = nullptr;
-    int sched_group = 0;
+    // rows per locality group of the chunk order (one strip of a tiled
+    // lattice numbering; 0 = none): the workgroups of one group share an XCD
+    int64_t group_rows = 0;
 };
 
 struct Stencil {
@@ -76,14 +74,10 @@ struct chebfd_ctx {
     // launch configuration of the fused step (chebfd_set_tuning)
     int tune_lpr = 0;     // lanes per row/site: 0 = default (32), 16, 32, 64
     int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
-    int tune_order = -1;  // -1 automatic, 0 slab-major, 1 chunk-major, 2 lattice z-march
-    int tune_gathers = 16; // gathers in flight per row (SELL): 8 or 16
-    int tune_pipeline = 0;  // SELL: one row block per workgroup (0) or the persistent pipelined kernel (1)
-    int tune_slab_group = 0; // SELL: slabs per group (0 = from order), a power of two
+    int tune_order = -1;  // matrix-free step: -1 automatic, 0 slab-major, 1 tiled lattice order
     int tune_pair_rows = 1; // SELL build: pair rows with equal gather columns in a chunk
-    int tune_waves = 5;     // SELL: occupancy target of the staged kernel (waves per SIMD), 4 or 5
-    int tune_batches = 1;   // stencil: neighbour loads in 1 batch or 2 (in-plane, then z)
     int tune_xcd_group = 0; // consecutive workgroups per XCD: 0 = default, 1 = hardware order
+    int tune_tile = -1;     // strip width (sites along x) of the tiled lattice order: -1 default, 0 off
 };
 
 struct chebfd_matrix {
@@ -98,6 +92,8 @@ struct chebfd_matrix {
 namespace chebfd {
 
 // scratch management (grows on demand; synchronises the stream before growing)
+int default_tile(const chebfd_ctx *ctx);
+bool tiled_order_pays(const int L[3], int64_t slab_row);
 int ensure_scratch(chebfd_ctx *ctx, size_t bytes);
 int ensure_pinned(chebfd_ctx *ctx, size_t bytes);
 

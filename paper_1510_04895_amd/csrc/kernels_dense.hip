@@ -298,49 +298,75 @@ __global__ void k_convert(const TI *__restrict__ X, TO *__restrict__ Y, int64_t 
 
 inline unsigned nblocks(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
 
-// Attainable-bandwidth probes (the read-only reduction of Sec. 4.1 and a
-// copy): grid-stride loops over 16-byte elements.
+// Attainable-bandwidth probes (the read-only reduction of Sec. 4.1, a copy,
+// and the fused step's five streams without the gather).  A workgroup owns
+// one contiguous tile of 256 x PU 16-byte elements and issues all PU
+// accesses of a lane before the first use, so every lane keeps PU requests
+// in flight; streamed data carries the non-temporal hint, as in the step.
 typedef double pd2 __attribute__((ext_vector_type(2)));
+constexpr int PU = 4;
 
 __global__ __launch_bounds__(256) void k_read_reduce(const pd2 *__restrict__ p, int64_t n16,
                                                      double *__restrict__ out)
 {
+    const int64_t base = (int64_t)blockIdx.x * (256 * PU) + threadIdx.x;
+    pd2 v[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+        const int64_t i = base + 256 * k;
+        v[k] = i < n16 ? __builtin_nontemporal_load(p + i) : pd2{0.0, 0.0};
+    }
     double s = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
-        const pd2 v = __builtin_nontemporal_load(p + i);
-        s += v.x + v.y;
-    }
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int k = 0; k < PU; ++k) s += v[k].x + v[k].y;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ __launch_bounds__(256) void k_copy16(const pd2 *__restrict__ src, pd2 *__restrict__ dst,
                                                 int64_t n16)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    const int64_t base = (int64_t)blockIdx.x * (256 * PU) + threadIdx.x;
+    pd2 v[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) v[k] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
+    }
 }
 
 // The fused step's streams without the gather: read u, w, x; write
-// w = 2u - w and x = x + w (three reads, two writes per element).
+// w = 2u - w and x = x + w/2 (three reads, two writes per element).
 __global__ __launch_bounds__(256) void k_stream_3r2w(const pd2 *__restrict__ u, pd2 *w, pd2 *x,
                                                      int64_t n16)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
-        const pd2 a = u[i];
-        const pd2 b = __builtin_nontemporal_load(w + i);
-        const pd2 c = __builtin_nontemporal_load(x + i);
-        const pd2 wn = 2.0 * a - b;
-        __builtin_nontemporal_store(wn, w + i);
-        __builtin_nontemporal_store(c + 0.5 * wn, x + i);
+    const int64_t base = (int64_t)blockIdx.x * (256 * PU) + threadIdx.x;
+    pd2 a[PU], b[PU], c[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) {
+            a[k] = u[i];
+            b[k] = __builtin_nontemporal_load(w + i);
+            c[k] = __builtin_nontemporal_load(x + i);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) {
+            const pd2 wn = 2.0 * a[k] - b[k];
+            __builtin_nontemporal_store(wn, w + i);
+            __builtin_nontemporal_store(c[k] + 0.5 * wn, x + i);
+        }
     }
 }
 
@@ -499,12 +525,12 @@ int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, 
 int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs)
 {
     const int64_t n16 = bytes / 16;
-    const unsigned grid = (unsigned)(ctx->num_cu * 16);
-    int rc = ensure_scratch(ctx, (size_t)grid * sizeof(double));
+    const int64_t half = n16 / 2, third = n16 / 3;
+    auto tiles = [](int64_t m) { return (unsigned)((m + 256 * PU - 1) / (256 * PU)); };
+    int rc = ensure_scratch(ctx, (size_t)tiles(n16) * sizeof(double));
     if (rc) return rc;
     double *part = (double *)ctx->scratch;
     pd2 *p = (pd2 *)buf;
-    const int64_t half = n16 / 2, third = n16 / 3;
     hipEvent_t e0, e1;
     CHEBFD_HIP(hipEventCreate(&e0));
     CHEBFD_HIP(hipEventCreate(&e1));
@@ -513,12 +539,14 @@ int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, 
         for (int r = -1; r < reps; ++r) {   // r = -1: warm-up
             if (r == 0) CHEBFD_HIP(hipEventRecord(e0, ctx->stream));
             if (which == 0)
-                hipLaunchKernelGGL(k_read_reduce, dim3(grid), dim3(256), 0, ctx->stream, p, n16, part);
+                hipLaunchKernelGGL(k_read_reduce, dim3(tiles(n16)), dim3(256), 0, ctx->stream, p,
+                                   n16, part);
             else if (which == 1)
-                hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, ctx->stream, p, p + half, half);
+                hipLaunchKernelGGL(k_copy16, dim3(tiles(half)), dim3(256), 0, ctx->stream, p,
+                                   p + half, half);
             else
-                hipLaunchKernelGGL(k_stream_3r2w, dim3(grid), dim3(256), 0, ctx->stream, p,
-                                   p + third, p + 2 * third, third);
+                hipLaunchKernelGGL(k_stream_3r2w, dim3(tiles(third)), dim3(256), 0, ctx->stream,
+                                   p, p + third, p + 2 * third, third);
         }
         CHEBFD_HIP(hipEventRecord(e1, ctx->stream));
         CHEBFD_HIP(hipEventSynchronize(e1));

@@ -12,6 +12,7 @@
 //   -t/2 ( G0[o][o] u[o] + d i Gj[o][o'] u[o'] ),
 // with o' the single orbital coupled by Gj: tau flipped, and s flipped for
 // j = x, y (s_x = 1, s_y = -i/+i) or kept for j = z (s_z = +1/-1).
+#include <algorithm>
 #include <type_traits>
 
 #include "dispatch.h"
@@ -69,14 +70,14 @@ __device__ __forceinline__ void add_hop(Pack<T, NB> (&acc)[4], const Site<T, NB>
     }
 }
 
-template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT, int NBATCH>
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
 __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc, T th, T mm,
                                                  const T *__restrict__ pot, int64_t nsites,
                                                  int64_t nblk, const T *__restrict__ u,
                                                  const T *wold, T *wout, T *y, int64_t n_s,
                                                  int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
                                                  double *__restrict__ partials, int order,
-                                                 int64_t nslab, int lg_xg)
+                                                 int64_t nslab, int lg_xg, int tile)
 {
     constexpr int SPW = 64 / LPS;   // sites per wave
     constexpr int SPB = 4 * SPW;    // sites per workgroup
@@ -87,30 +88,30 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x, lg_xg);
     int64_t slab, sb, site;
     bool in_lattice;
-    if (order == 2) {
-        // z-march: a block is SPB x-consecutive sites of one (y, z); the
-        // logical order runs z fastest, then x-blocks, then y, then slabs, so
-        // the z-neighbour planes of a block were gathered by the block just
-        // before it (on the same XCD when 2^lg_xg consecutive blocks share one)
-        const int64_t nxb = (Lx + SPB - 1) / SPB;
-        const int64_t nper = nxb * Ly * Lz;
+    if (order == 1) {
+        // tiled lattice order: a block is SPB z-consecutive sites of one
+        // (x, y) column; z-blocks run fastest, then the `tile` x-columns of
+        // a strip, then y, then strips, then slabs (tile divides Lx), so
+        // every neighbour of a site is gathered at most one strip-row of
+        // work apart, on the XCD that runs the strip
+        const int64_t nzb = (Lz + SPB - 1) / SPB;
+        const int64_t per_strip = (int64_t)tile * Ly * nzb;
+        const int64_t nper = (Lx / tile) * per_strip;
         slab = b / nper;
         sb = b - slab * nper;
-        const int64_t t = sb / Lz;
-        const int z = (int)(sb - t * Lz);
-        const int64_t yb = t / nxb;
-        const int xb = (int)(t - yb * nxb);
-        const int x = xb * SPB + wave * SPW + ssub;
-        in_lattice = x < Lx;
-        site = x + (int64_t)Lx * (yb + (int64_t)Ly * z);
+        const int64_t strip = sb / per_strip;
+        const int64_t r = sb - strip * per_strip;
+        const int64_t t = r / nzb;
+        const int zb = (int)(r - t * nzb);
+        const int64_t yy0 = t / tile;
+        const int xl = (int)(t - yy0 * tile);
+        const int z = zb * SPB + wave * SPW + ssub;
+        in_lattice = z < Lz;
+        site = (strip * tile + xl) + (int64_t)Lx * (yy0 + (int64_t)Ly * z);
     } else {
-        if (order == 0) {
-            slab = b / nblk;
-            sb = b - slab * nblk;
-        } else {
-            sb = b / nslab;
-            slab = b - sb * nslab;
-        }
+        // column-slab major, sites in lattice order
+        slab = b / nblk;
+        sb = b - slab * nblk;
         site = sb * SPB + wave * SPW + ssub;
         in_lattice = site < nsites;
     }
@@ -129,20 +130,16 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
         const int yy = (int)(rem / Lx);
         const int x = (int)(rem - (int64_t)yy * Lx);
         const Site<T, NB> uo = load_site<T, NB>(u, site, ld, c0, cnt);
-        // streamed operands of the four output rows, issued with the first
-        // batch (NBATCH = 1) or the second (NBATCH = 2, fewer registers)
+        // streamed operands of the four output rows
         Site<T, NB> wo, yo;
-        auto load_streams = [&]() {
-            if (MODE == MODE_SECOND || MODE == MODE_STEP)
+        if (MODE == MODE_SECOND || MODE == MODE_STEP)
 #pragma unroll
-                for (int o = 0; o < 4; ++o)
-                    wo.o[o] = load_pack_n<T, NB, NT>(wold + 2 * ((4 * site + o) * ld + c0), cnt);
-            if (MODE == MODE_STEP)
+            for (int o = 0; o < 4; ++o)
+                wo.o[o] = load_pack_n<T, NB, NT>(wold + 2 * ((4 * site + o) * ld + c0), cnt);
+        if (MODE == MODE_STEP)
 #pragma unroll
-                for (int o = 0; o < 4; ++o)
-                    yo.o[o] = load_pack_n<T, NB, NT>(y + 2 * ((4 * site + o) * ld + c0), cnt);
-        };
-        if (NBATCH == 1) load_streams();
+            for (int o = 0; o < 4; ++o)
+                yo.o[o] = load_pack_n<T, NB, NT>(y + 2 * ((4 * site + o) * ld + c0), cnt);
         const T vn = pot[site];
         Pack<T, NB> acc[4];
 #pragma unroll
@@ -156,8 +153,7 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
         }
         // The six neighbours, branch-free: a missing neighbour (open
         // boundary) reads the site itself with hopping weight 0.  All their
-        // rows are requested before the first one is used (NBATCH = 1), or
-        // the in-plane ones first and the z pair second (NBATCH = 2).
+        // rows are requested before the first one is used.
         int64_t nb[6];
         T tw[6];
         {
@@ -178,7 +174,7 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                 tw[2 * j + 1] = okm ? th : T(0);
             }
         }
-        if (NBATCH == 1) {
+        {
             Site<T, NB> un[6];
 #pragma unroll
             for (int j = 0; j < 6; ++j) un[j] = load_site<T, NB>(u, nb[j], ld, c0, cnt);
@@ -189,26 +185,6 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
             add_hop<T, NB, 1>(acc, un[3], tw[3], T(-1));
             add_hop<T, NB, 2>(acc, un[4], tw[4], T(1));
             add_hop<T, NB, 2>(acc, un[5], tw[5], T(-1));
-        } else {
-            {
-                Site<T, NB> un[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) un[j] = load_site<T, NB>(u, nb[j], ld, c0, cnt);
-                __builtin_amdgcn_sched_barrier(0);
-                add_hop<T, NB, 0>(acc, un[0], tw[0], T(1));
-                add_hop<T, NB, 0>(acc, un[1], tw[1], T(-1));
-                add_hop<T, NB, 1>(acc, un[2], tw[2], T(1));
-                add_hop<T, NB, 1>(acc, un[3], tw[3], T(-1));
-            }
-            {
-                Site<T, NB> un[2];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) un[j] = load_site<T, NB>(u, nb[4 + j], ld, c0, cnt);
-                load_streams();
-                __builtin_amdgcn_sched_barrier(0);
-                add_hop<T, NB, 2>(acc, un[0], tw[4], T(1));
-                add_hop<T, NB, 2>(acc, un[1], tw[5], T(-1));
-            }
         }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
@@ -308,16 +284,14 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
 // z-neighbour of the plane above and, two planes of work later, of the plane
 // below; in between the step moves two planes of its five block streams over
 // one slab.  Once that exceeds the memory-side cache (256 MB on MI355X) the
-// second gather goes back to HBM, and the z-march, which runs the planes of
-// one z-column back to back, wins (measured: 10-12% at 128x128x64 and
-// 256x256x64 with 256/128 columns, a loss at 64x64x32).
+// second gather goes back to HBM, and the tiled order (strips of x-columns,
+// z fastest: every neighbour at most one strip-row of work away, one strip
+// per XCD) wins: 256x256x64 with 128 columns in complex128, 38.0 ms
+// slab-major against 29.3 ms tiled.
 template <typename T, int SW>
 int auto_order(const Stencil &S, int64_t n_s)
 {
-    constexpr double kMallBytes = 256.0 * (1 << 20);
-    const double slab_row = (double)(n_s < SW ? n_s : SW) * 2 * sizeof(T);
-    const double between = 2.0 * S.L[0] * S.L[1] * 4 * 5 * slab_row;
-    return between > kMallBytes ? 2 : 0;
+    return tiled_order_pays(S.L, (int64_t)(n_s < SW ? n_s : SW) * 2 * sizeof(T)) ? 1 : 0;
 }
 
 template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
@@ -326,25 +300,28 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     constexpr int SPB = 4 * (64 / LPS);
     constexpr int SW = LPS * NB;
     const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
-    const int order = ctx->tune_order >= 0 ? ctx->tune_order : auto_order<T, SW>(S, a.n_s);
-    // z-march blocks cover whole x-runs of SPB sites (the last one ragged)
-    const int64_t nblk = order == 2 ? (S.L[0] + SPB - 1) / SPB * S.L[1] * S.L[2]
-                                    : (nsites + SPB - 1) / SPB;
+    int order = ctx->tune_order >= 0 ? ctx->tune_order : auto_order<T, SW>(S, a.n_s);
+    // tiled order: the largest strip width up to the default that divides Lx
+    int tile = std::min(default_tile(ctx), S.L[0]);
+    while (tile > 1 && S.L[0] % tile) --tile;
+    if (order == 1 && tile < 1) order = 0;
+    const int64_t nzb = (S.L[2] + SPB - 1) / SPB;
+    // tiled blocks cover z-runs of SPB sites (the last one of a column ragged)
+    const int64_t nblk = order == 1 ? (int64_t)S.L[0] * S.L[1] * nzb : (nsites + SPB - 1) / SPB;
     const int64_t nslab = (a.n_s + SW - 1) / SW;
     if (nblk * nslab >= ((int64_t)1 << 31))
         return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
     if (n_part) *n_part = nblk;
-    // default placement for the z-march: one z-column of blocks per XCD group
+    // default placement in the tiled order: one strip of blocks per XCD group
     int lg_xg = ilog2(ctx->tune_xcd_group);
-    if (order == 2 && !ctx->tune_xcd_group) lg_xg = ilog2(S.L[2]);
+    if (order == 1 && !ctx->tune_xcd_group) lg_xg = ilog2_64((int64_t)tile * S.L[1] * nzb);
     const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
-    const auto kern = ctx->tune_batches == 2 ? k_step_ti<T, LPS, NB, MODE, MOM, NT, 2>
-                                             : k_step_ti<T, LPS, NB, MODE, MOM, NT, 1>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(nblk * nslab)),
+    hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
                        dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,
                        (T)(-0.5 * S.t), (T)S.m, pot, nsites, nblk, (const T *)a.u,
                        (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld, (T)a.s_h,
-                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, order, nslab, lg_xg);
+                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, order, nslab, lg_xg,
+                       tile);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }

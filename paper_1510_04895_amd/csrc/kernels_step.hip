@@ -15,7 +15,9 @@
 // w and x are read and written only at the workgroup's own rows, so the
 // in-place updates are race-free.  Workgroups are ordered slab-major (all
 // chunks of slab 0, then slab 1, ...) so the cache working set of u is one
-// slab wide.
+// slab wide; the chunk order itself is the matrix's row order (for large
+// lattices a tiled order, built with the matrix).
+#include <algorithm>
 #include <type_traits>
 
 #include "dispatch.h"
@@ -161,30 +163,16 @@ struct BlockLoc {
     int64_t base;
 };
 
-// Logical work item l -> block.  `order` is the slab-group size G: the
-// column slabs are taken G at a time, and inside a group the G slabs of a
-// row block run back to back (G = 1: slab-major, G = nslab: block-major), so
-// a row block's index stream is staged from memory once per group and from
-// L2 for the other slabs of the group.  The row blocks per chunk are a
-// power of two (2^lg_bpc).  With a schedule, the row blocks visit the chunks
-// in the scheduled order.
-__device__ __forceinline__ BlockLoc locate(uint32_t l, int order, uint32_t nrb, uint32_t nslab,
-                                          int C, int lg_bpc, int RB,
+// Logical work item l -> block, slab-major: all row blocks of slab 0, then
+// slab 1, ...  The row blocks per chunk are a power of two (2^lg_bpc).
+__device__ __forceinline__ BlockLoc locate(uint32_t l, uint32_t nrb, int lg_bpc, int RB,
                                           const int64_t *__restrict__ chunk_ptr,
-                                          const int32_t *__restrict__ chunk_len,
-                                          const int32_t *__restrict__ sched)
+                                          const int32_t *__restrict__ chunk_len)
 {
     BlockLoc L;
-    // slab groups of G = order slabs: all row blocks of a group, each with
-    // the group's slabs adjacent (G = 1: slab-major, G = nslab: block-major)
-    const uint32_t G = (uint32_t)order;
-    const uint32_t per = nrb * G;
-    const uint32_t sg = l / per;
-    const uint32_t g = (nslab - sg * G) < G ? (nslab - sg * G) : G;
-    const uint32_t rem = l - sg * per;
-    L.rb = rem / g;
-    L.slab = sg * G + (rem - L.rb * g);
-    L.chunk = sched ? (uint32_t)sched[L.rb >> lg_bpc] : L.rb >> lg_bpc;
+    L.slab = l / nrb;
+    L.rb = l - L.slab * nrb;
+    L.chunk = L.rb >> lg_bpc;
     L.r0 = (L.rb & ((1u << lg_bpc) - 1)) * RB;
     L.len = chunk_len[L.chunk];
     L.base = chunk_ptr[L.chunk];
@@ -355,18 +343,15 @@ __device__ __forceinline__ void moment_partials(double (&m0)[NB], double (&m1)[N
     lds_barrier();   // red is reused by the next block
 }
 
-// One row block per workgroup (used for rows longer than the LDS stage,
-// which read the index stream directly, and as a tuning alternative).
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB,
-          int WAVES = 4>
-__global__ __launch_bounds__(256, WAVES) void k_step_sell(
+// One row block per workgroup; rows longer than the LDS stage read the
+// index stream directly.
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
+__global__ __launch_bounds__(256, 5) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
-    const int32_t *__restrict__ sched, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ col,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
     const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
     const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
-    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int order, uint32_t nslab,
-    int lg_xg)
+    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg)
 {
     constexpr int RPW = 64 / LPR;        // rows per wave
     constexpr int RPP = 4 * RPW;         // rows per workgroup
@@ -378,8 +363,8 @@ __global__ __launch_bounds__(256, WAVES) void k_step_sell(
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int rsub = lane / LPR, cl = lane % LPR;
-    const BlockLoc L = locate(xcd_remap(blockIdx.x, gridDim.x, lg_xg), order, nrb, nslab, C,
-                              lg_bpc, RB, chunk_ptr, chunk_len, sched);
+    const BlockLoc L = locate(xcd_remap(blockIdx.x, gridDim.x, lg_xg), nrb, lg_bpc, RB,
+                              chunk_ptr, chunk_len);
     {
         Stage<T, RPP> st;
         if (STAGED) {
@@ -402,76 +387,6 @@ __global__ __launch_bounds__(256, WAVES) void k_step_sell(
             row, c0, cnt, L.len, s_col + q, s_val + 2 * q, col, val, L.base + L.r0 + q, C, u,
             wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
     if (MOM) moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
-}
-
-// Persistent, software-pipelined form of the staged kernel: each workgroup
-// walks the logical work items v = blockIdx.x, + gridDim.x, ... (gridDim.x a
-// multiple of the XCD count, so a workgroup stays on one XCD's sequence) and
-// stages the next block's index/value stream into the other LDS buffer while
-// the current block's gathers are in flight.  The block metadata is fetched
-// two blocks ahead.
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, int GB>
-__global__ __launch_bounds__(256) void k_step_sell_pipe(
-    const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
-    const int32_t *__restrict__ sched, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ col,
-    const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
-    const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
-    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int order, uint32_t nslab,
-    int lg_xg)
-{
-    constexpr int RPW = 64 / LPR;
-    constexpr int RPP = 4 * RPW;
-    constexpr int SW = LPR * NB;
-    __shared__ __align__(16) int32_t s_col[2][RPP * LS];
-    __shared__ __align__(16) T s_val[2][2 * RPP * LS];
-    __shared__ int32_t s_row[2][RPP];
-    __shared__ double red[MOM ? 4 : 1][64][3 * NB];
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int rsub = lane / LPR, cl = lane % LPR;
-    const int q = wave * RPW + rsub;
-    const uint32_t total = nrb * nslab, G = gridDim.x;
-    auto at = [&](uint32_t v) {
-        return locate(xcd_remap(v, total, lg_xg), order, nrb, nslab, C, lg_bpc, RB, chunk_ptr,
-                      chunk_len, sched);
-    };
-    uint32_t v = blockIdx.x;
-    BlockLoc cur = at(v);
-    BlockLoc nxt = (v + G < total) ? at(v + G) : cur;
-    {
-        Stage<T, RPP> st;
-        stage_load<T, RPP>(st, cur, tid, C, RB, perm, col, val);
-        stage_store<T, RPP>(st, cur, tid, RB, s_col[0], s_val[0], s_row[0]);
-    }
-    lds_barrier();
-    int buf = 0;
-    for (; v < total; v += G) {
-        const bool has_next = v + G < total;
-        // next block's stream: issued before this block's gathers
-        Stage<T, RPP> st;
-        if (has_next) stage_load<T, RPP>(st, nxt, tid, C, RB, perm, col, val);
-        const int64_t c0 = (int64_t)cur.slab * SW + (int64_t)cl * NB;
-        const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);
-        const int row = s_row[buf][q];
-        double m0[NB], m1[NB], m2[NB];
-#pragma unroll
-        for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
-        if (c0 < n_s && row >= 0)
-            step_row<T, NB, MODE, MOM, NT, true, GB, RPP>(
-                row, c0, cnt, cur.len, s_col[buf] + q, s_val[buf] + 2 * q, col, val, 0, C, u,
-                wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
-        // metadata two blocks ahead; its latency is hidden by a whole block
-        const BlockLoc nn = (v + 2 * G < total) ? at(v + 2 * G) : nxt;
-        if (MOM)
-            moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, cur.rb, c0, cnt, n_s, partials);
-        if (has_next)
-            stage_store<T, RPP>(st, nxt, tid, RB, s_col[buf ^ 1], s_val[buf ^ 1], s_row[buf ^ 1]);
-        lds_barrier();
-        buf ^= 1;
-        cur = nxt;
-        nxt = nn;
-    }
 }
 
 // Moment finalisation: one workgroup per (column, quantity) sums the
@@ -527,11 +442,10 @@ int64_t sell_row_blocks(const Sell &S, int lpr)
     return S.nchunks * (S.C / rb);
 }
 
-// Launch geometry shared by both SELL kernels.
+// Launch geometry of the SELL kernel.
 struct SellGeom {
-    int RB, lg_bpc, lg_xg, order;
+    int RB, lg_bpc, lg_xg;
     uint32_t nrb, nslab;
-    const int32_t *sched;
 };
 
 template <int LPR, int NB>
@@ -545,61 +459,24 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
         return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
     g.RB = S.C < RPP ? S.C : RPP;
     g.lg_bpc = ilog2(S.C / g.RB);
-    // slab-group size (order 1: block-major; order 2 follows the matrix's
-    // chunk schedule, if it has one, slab-major)
-    int G = ctx->tune_order == 1 ? (int)nslab : 1;
-    if (ctx->tune_slab_group > 0) G = (int)std::min<int64_t>(ctx->tune_slab_group, nslab);
-    g.order = G;
-    g.sched = ctx->tune_order == 2 ? S.sched : nullptr;
-    // default placement: the row blocks of one chunk (and the slabs of a
-    // group) share an XCD; under a schedule, one locality group of chunks does
-    int grp = S.C / g.RB;
-    if (G > 1) grp *= G;
-    if (g.sched && S.sched_group > 0) grp *= S.sched_group;
-    g.lg_xg = ilog2(ctx->tune_xcd_group ? ctx->tune_xcd_group : grp);
+    // default placement: the row blocks of one chunk share an XCD, or, in a
+    // tiled lattice order, the row blocks of one strip
+    const int64_t grp = S.group_rows > 0 ? S.group_rows / g.RB : S.C / g.RB;
+    g.lg_xg = ctx->tune_xcd_group ? ilog2(ctx->tune_xcd_group) : ilog2_64(grp);
     g.nrb = (uint32_t)nrb;
     g.nslab = (uint32_t)nslab;
     return CHEBFD_OK;
 }
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB,
-          int WAVES = 4>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
 void launch_sell_k(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
 {
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB, WAVES>),
+    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB>),
                        dim3(g.nrb * g.nslab), dim3(256), 0, ctx->stream, S.chunk_ptr,
-                       S.chunk_len, g.sched, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
+                       S.chunk_len, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
                        (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
-                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.order,
-                       g.nslab, g.lg_xg);
-}
-
-// Persistent launch: as many workgroups as fit on the device at once (a
-// multiple of the XCD count), each walking its sequence of blocks.
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, int GB>
-void launch_sell_pipe(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
-{
-    const auto kern = k_step_sell_pipe<T, LPR, NB, MODE, MOM, NT, GB>;
-    static int per_cu = 0;   // resident workgroups per CU of this instantiation
-    if (!per_cu) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kern, 256, 0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 1;
-        per_cu = nb;
-    }
-    const int64_t total = (int64_t)g.nrb * g.nslab;
-    int64_t grid = (int64_t)ctx->num_cu * per_cu / NUM_XCD * NUM_XCD;
-    if (grid > total) grid = total;
-    if (grid < 1) grid = 1;
-    const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, ctx->stream, S.chunk_ptr,
-                       S.chunk_len, g.sched, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
-                       (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
-                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.order,
-                       g.nslab, g.lg_xg);
+                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.lg_xg);
 }
 
 template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT>
@@ -607,18 +484,8 @@ int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
 {
     SellGeom g;
     if (int rc = sell_geom<LPR, NB>(ctx, S, a, g)) return rc;
-    // rows that fit the LDS stage -> staged variant (persistent and
-    // pipelined by default), else the index stream
-    const bool staged = S.max_len <= LS;
-    if (staged && ctx->tune_pipeline && ctx->tune_gathers == 8)
-        launch_sell_pipe<T, LPR, NB, MODE, MOM, NT, 8>(ctx, S, a, g);
-    else if (staged && ctx->tune_pipeline)
-        launch_sell_pipe<T, LPR, NB, MODE, MOM, NT, 16>(ctx, S, a, g);
-    else if (staged && ctx->tune_gathers == 8)
-        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 8>(ctx, S, a, g);
-    else if (staged && ctx->tune_waves == 5)
-        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16, 5>(ctx, S, a, g);
-    else if (staged)
+    // rows that fit the LDS stage -> staged variant, else the index stream
+    if (S.max_len <= LS)
         launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16>(ctx, S, a, g);
     else
         launch_sell_k<T, LPR, NB, MODE, MOM, NT, false, 8>(ctx, S, a, g);
@@ -693,12 +560,12 @@ int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int p
     const int nb = precision == CHEBFD_PREC_C128 ? 1 : 2;
     const int lpr = pick_lpr(ctx, n_s, nb);
     if (H->storage == CHEBFD_STORAGE_SELL) return sell_row_blocks(H->sell, lpr);
-    // the larger of the two stencil block counts (site-linear and z-march)
+    // the larger of the two stencil block counts (site-linear and tiled)
     const Stencil &T = H->st;
     const int64_t spb = 4 * (64 / lpr);
     const int64_t lin = (H->n / 4 + spb - 1) / spb;
-    const int64_t zm = (T.L[0] + spb - 1) / spb * T.L[1] * T.L[2];
-    return lin > zm ? lin : zm;
+    const int64_t tl = (int64_t)T.L[0] * T.L[1] * ((T.L[2] + spb - 1) / spb);
+    return std::max(lin, tl);
 }
 
 int launch_moment_finalize(chebfd_ctx *ctx, const double *partials, int64_t n_part,

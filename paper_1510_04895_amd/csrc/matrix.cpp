@@ -93,14 +93,17 @@ void free_matrix(chebfd_matrix *H)
 {
     Sell &S = H->sell;
     for (void *p : {(void *)S.chunk_ptr, (void *)S.chunk_len, (void *)S.perm, (void *)S.col,
-                    (void *)S.val64, (void *)S.val32, (void *)S.sched, (void *)H->st.pot64,
+                    (void *)S.val64, (void *)S.val32, (void *)H->st.pot64,
                     (void *)H->st.pot32})
         if (p) (void)hipFree(p);
 }
 
 // Builds SELL-C-sigma from a row generator.  rowfn(i, entries) fills row i.
+// `order` (optional) is the sequence in which rows are cut into sigma windows
+// and chunks (the traversal order of the fused step); nullptr = 0, 1, ...
 template <typename RowFn>
-int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool pair_rows)
+int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool pair_rows,
+               const std::vector<int32_t> *order = nullptr)
 {
     Sell &S = H->sell;
     S.n = n;
@@ -133,7 +136,8 @@ int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool 
     for (int64_t w0 = 0; w0 < n; w0 += sigma) {
         const int64_t w1 = std::min(n, w0 + sigma);
         std::vector<int32_t> ids(w1 - w0);
-        std::iota(ids.begin(), ids.end(), (int32_t)w0);
+        if (order) std::copy(order->begin() + w0, order->begin() + w1, ids.begin());
+        else std::iota(ids.begin(), ids.end(), (int32_t)w0);
         std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
         std::copy(ids.begin(), ids.end(), perm.begin() + w0);
     }
@@ -230,34 +234,42 @@ int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool 
     return CHEBFD_OK;
 }
 
-// Lattice traversal order of the chunks of a TI matrix: chunks are keyed by
-// the site of their first row as (y, x-run, z) with z fastest, so that
-// consecutive scheduled chunks are z-neighbours and a z-column of chunks
-// forms one locality group.
-int build_ti_schedule(chebfd_matrix *H, const int L[3])
+// Tiled lattice order of the rows: the lattice is cut into strips of `w`
+// x-columns; strips run one after the other, inside a strip y-rows, inside a
+// y-row the x-columns, and along each column z fastest, the four orbital rows
+// of a site together.  Consecutive chunks are then z-runs of one column, and
+// every neighbour of a site is at most one strip-row of work away.
+std::vector<int32_t> ti_tiled_rows(const int L[3], int w)
 {
-    Sell &S = H->sell;
-    const int64_t run = std::max(1, S.C / 4);
-    const int64_t nxb = (L[0] + run - 1) / run;
-    std::vector<int64_t> key(S.nchunks);
-    std::vector<int32_t> perm((size_t)S.nchunks * S.C);
-    CHEBFD_HIP(hipMemcpy(perm.data(), S.perm, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    for (int64_t c = 0; c < S.nchunks; ++c) {
-        int64_t i = -1;
-        for (int r = 0; r < S.C && i < 0; ++r) i = perm[c * S.C + r];
-        if (i < 0) i = 0;
-        const int64_t site = i / 4, x = site % L[0], y = (site / L[0]) % L[1],
-                      z = site / ((int64_t)L[0] * L[1]);
-        key[c] = ((y * nxb + x / run) * L[2] + z);
-    }
-    std::vector<int32_t> order(S.nchunks);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-    S.sched_group = L[2];
-    return upload(&S.sched, order);
+    std::vector<int32_t> r;
+    r.reserve((size_t)4 * L[0] * L[1] * L[2]);
+    for (int x0 = 0; x0 < L[0]; x0 += w)
+        for (int y = 0; y < L[1]; ++y)
+            for (int x = x0; x < std::min(L[0], x0 + w); ++x)
+                for (int z = 0; z < L[2]; ++z) {
+                    const int64_t site = x + (int64_t)L[0] * (y + (int64_t)L[1] * z);
+                    for (int o = 0; o < 4; ++o) r.push_back((int32_t)(4 * site + o));
+                }
+    return r;
 }
 
 }  // namespace
+
+// Default strip width of the tiled lattice order (sites along x).
+int default_tile(const chebfd_ctx *ctx)
+{
+    return ctx->tune_tile >= 0 ? ctx->tune_tile : 4;
+}
+
+// Whether the tiled lattice order pays: in column-slab-major order a site's
+// u row is gathered again two lattice planes of work later, during which the
+// step moves two planes of its five block streams (slab_row bytes per row);
+// beyond the 256 MB memory-side cache that second gather returns to HBM.
+bool tiled_order_pays(const int L[3], int64_t slab_row)
+{
+    constexpr double kMallBytes = 256.0 * (1 << 20);
+    return 2.0 * L[0] * L[1] * 4 * 5 * (double)slab_row > kMallBytes;
+}
 
 }  // namespace chebfd
 
@@ -336,8 +348,16 @@ extern "C" int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc
     };
     int rc = CHEBFD_OK;
     if (storage == CHEBFD_STORAGE_SELL) {
-        rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
-        if (rc == CHEBFD_OK) rc = build_ti_schedule(H, L);
+        // the fused step's slab row: 32 lanes of 16 bytes
+        const int w = ctx->tune_tile >= 0 || tiled_order_pays(L, 512)
+                          ? std::min(default_tile(ctx), Lx) : 0;
+        if (w > 0) {
+            const std::vector<int32_t> order = ti_tiled_rows(L, w);
+            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0, &order);
+            H->sell.group_rows = (int64_t)4 * w * Ly * Lz;
+        } else {
+            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
+        }
     } else {
         Stencil &S = H->st;
         S.L[0] = Lx;

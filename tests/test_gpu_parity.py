@@ -132,16 +132,15 @@ def test_filter_c64_vs_reference(env, orc, storage):
     assert relerr(got, ref) < tol
 
 
-@pytest.mark.parametrize("kind", ["ti", "csr"])
+@pytest.mark.parametrize("kind,tile", [("ti", 0), ("ti", 4), ("ti", 5), ("csr", -1)])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("pipeline", [0, 1])
-def test_filter_many_blocks_per_workgroup(env, orc, kind, prec, pipeline):
-    """Large enough that every persistent workgroup of the pipelined SELL
-    kernel walks many row blocks (tens of thousands of blocks for about a
-    thousand resident workgroups), with a ragged last chunk and moments on;
-    the default one-block-per-workgroup kernel on the same inputs."""
+def test_filter_many_blocks_per_workgroup(env, orc, kind, tile, prec):
+    """Tens of thousands of row blocks, a ragged last chunk and moments on;
+    the TI matrix in lattice row order and in the tiled row order (strips of
+    4 or 5 x-columns, the latter leaving a ragged last strip), the random
+    matrix in its own order."""
     torch, B, ctx = env
-    B.chebfd_set_tuning(ctx, "pipeline", pipeline)
+    B.chebfd_set_tuning(ctx, "tile", tile)
     if kind == "ti":
         L = (24, 24, 23)
         Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=6)
@@ -166,7 +165,7 @@ def test_filter_many_blocks_per_workgroup(env, orc, kind, prec, pipeline):
         B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom)
         torch.cuda.synchronize()
     finally:
-        B.chebfd_set_tuning(ctx, "pipeline", 0)
+        B.chebfd_set_tuning(ctx, "tile", -1)
     got = Xd.cpu().numpy().astype(np.complex128)
     m = mom.cpu().numpy()
     if prec == "c128":
@@ -179,75 +178,93 @@ def test_filter_many_blocks_per_workgroup(env, orc, kind, prec, pipeline):
 
 @pytest.mark.parametrize("storage", ["sell", "stencil"])
 def test_launch_settings_give_identical_blocks(env, storage):
-    """Every launch setting computes each output element with the same
-    operations in the same order, so the filtered blocks agree bit for bit;
-    the moment sums (reduced over a setting-dependent tree) agree to
-    rounding."""
+    """Every launch setting and every SELL row order computes each output
+    element with the same operations in the same order, so the filtered
+    blocks agree bit for bit; the moment sums (reduced over a
+    setting-dependent tree) agree to rounding."""
     torch, B, ctx = env
     st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
     L = (16, 16, 15)
-    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=3, storage=st)
-    info = H.info()
-    a, b = info["g_lo"], info["g_hi"]
     n_s, n_p = 96, 7
-    X0 = to_dev(torch, inp.random_block(info["n"], n_s, seed=5))
     gam = inp.random_gamma(n_p, seed=6)
-    settings = [dict(), dict(lanes=64), dict(lanes=16), dict(order=1), dict(xcd_group=1),
-                dict(xcd_group=8, order=1), dict(gathers=8), dict(pipeline=1),
-                dict(pipeline=1, gathers=8, lanes=64), dict(order=2), dict(order=2, lanes=64),
-                dict(order=2, pipeline=1, xcd_group=4), dict(batches=2),
-                dict(batches=2, lanes=64), dict(waves=4), dict(slab_group=2),
-                dict(slab_group=4, lanes=16), dict(slab_group=2, pipeline=1), dict(order=0)]
-    defaults = dict(lanes=0, order=-1, xcd_group=0, gathers=16, pipeline=0, batches=1, waves=5,
-                    slab_group=0)
+    if storage == "sell":
+        # (build-time tile, launch settings): lattice and tiled row orders
+        settings = [(0, dict()), (0, dict(lanes=64)), (0, dict(lanes=16)),
+                    (0, dict(xcd_group=1)), (0, dict(xcd_group=8)), (4, dict()),
+                    (2, dict(lanes=64)), (5, dict(xcd_group=1)), (4, dict(nontemporal=0)),
+                    (0, dict(pair_rows=0))]
+    else:
+        settings = [(-1, dict()), (-1, dict(lanes=64)), (-1, dict(lanes=16)),
+                    (-1, dict(xcd_group=1)), (-1, dict(order=0)), (-1, dict(order=1)),
+                    (2, dict(order=1, lanes=64)), (16, dict(order=1, xcd_group=1)),
+                    (4, dict(order=1, lanes=16)), (-1, dict(order=1, nontemporal=0))]
+    defaults = dict(lanes=0, order=-1, xcd_group=0, nontemporal=1, pair_rows=1)
     outs, moms = [], []
     try:
-        for cfg in settings:
+        for tile, cfg in settings:
             for k, v in {**defaults, **cfg}.items():
                 B.chebfd_set_tuning(ctx, k, v)
-            Xd = X0.clone()
+            B.chebfd_set_tuning(ctx, "tile", tile)
+            H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=3, storage=st)
+            info = H.info()
+            a, b = info["g_lo"], info["g_hi"]
+            Xd = to_dev(torch, inp.random_block(info["n"], n_s, seed=5))
             Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
             mom = torch.zeros((2 * n_p + 1, n_s), dtype=torch.float64, device="cuda")
             B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom)
             torch.cuda.synchronize()
             outs.append(Xd.cpu().numpy())
             moms.append(mom.cpu().numpy())
+            del H
     finally:
         for k, v in defaults.items():
             B.chebfd_set_tuning(ctx, k, v)
+        B.chebfd_set_tuning(ctx, "tile", -1)
     for cfg, o, m in zip(settings, outs, moms):
         assert np.array_equal(o, outs[0]), cfg
         assert np.abs(m - moms[0]).max() < 1e-12 * np.abs(moms[0][0]).max(), cfg
 
 
+@pytest.mark.parametrize("storage", ["sell", "stencil"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_automatic_order_on_wide_lattice(env, prec):
+def test_automatic_order_on_wide_lattice(env, orc, storage, prec):
     """A 128x128 plane puts 320 MiB of slab-major traffic between a site's
-    two z-neighbour gathers, so the default order runs the matrix-free step
-    as a z-march; the filtered block is bitwise the one of the explicit
-    slab-major and z-march orders."""
+    two z-neighbour gathers, so by default the matrix-free step runs in the
+    tiled lattice order and the SELL matrix is built in the tiled row order;
+    the filtered block equals the oracle's and, bit for bit, the one of the
+    lattice order."""
     torch, B, ctx = env
-    H = B.Matrix.ti(ctx, (128, 128, 3), pbc=3, V=1.0, seed=4, storage=B.STORAGE_STENCIL)
-    info = H.info()
-    a, b = info["g_lo"], info["g_hi"]
+    L = (128, 128, 3)
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
     n_s = 32 if prec == "c128" else 64
-    X0 = to_dev(torch, inp.random_block(info["n"], n_s, seed=8),
-                dtype=torch.complex64 if prec == "c64" else None)
+    X = inp.random_block(4 * L[0] * L[1] * L[2], n_s, seed=8)
+    if prec == "c64":
+        X = X.astype(np.complex64).astype(np.complex128)
     gam = inp.random_gamma(5, seed=9)
     outs = []
     try:
-        for order in (-1, 0, 2):
+        for tile, order in ((-1, -1), (0, 0), (-1, 0)):
+            B.chebfd_set_tuning(ctx, "tile", tile)
             B.chebfd_set_tuning(ctx, "order", order)
-            Xd = X0.clone()
+            H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=4, storage=st)
+            info = H.info()
+            a, b = info["g_lo"], info["g_hi"]
+            Xd = to_dev(torch, X, dtype=torch.complex64 if prec == "c64" else None)
             Ud, Wd = torch.zeros_like(Xd), torch.zeros_like(Xd)
             B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
             torch.cuda.synchronize()
-            outs.append(Xd.cpu().numpy())
+            outs.append(Xd.cpu().numpy().astype(np.complex128))
+            del H
     finally:
+        B.chebfd_set_tuning(ctx, "tile", -1)
         B.chebfd_set_tuning(ctx, "order", -1)
     assert np.array_equal(outs[0], outs[1])
     assert np.array_equal(outs[0], outs[2])
-    assert np.isfinite(outs[0]).all() and np.abs(outs[0]).max() > 0
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=4)
+    a, b = orc.gershgorin(Hr)
+    ref = orc.filter_block(Hr, a, b, gam, X)
+    tol = 1e-12 * 5 if prec == "c128" else 30 * math.sqrt(5) * 2.0 ** -24
+    assert relerr(outs[0], ref) < tol
 
 
 def test_filter_full_block_equals_column_subset(env, orc):
