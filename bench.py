@@ -1,19 +1,25 @@
-"""Benchmark: fused Chebyshev SpMMV throughput and time to all window
-eigenpairs (residual < 1e-9) on one MI355X.
+"""Benchmark: fused Chebyshev SpMMV throughput on one MI355X, and time to
+all window eigenpairs (residual < 1e-9).
 
-    python bench.py [--steps K] [--warmup W] [--workload ti_64x64x32]
+    python bench.py [--steps K] [--warmup W] [--workload ti_256x256x64]
                     [--storage sell|stencil] [--precision c128|c64]
                     [--kernel-only] [--no-cpu-baseline]
 
-A step is one complete ChebFD solve (Sec. 3.1 steps 1-8: spectral bounds,
-filter coefficients, random block, N_p fused filter launches per iteration,
-orthogonalisation, Rayleigh-Ritz, residuals, locking, restart) on the
-synthetic topological-insulator lattice, with the matrix and all blocks
-resident in HBM when the timed region starts.  `value` is the algorithmic
-filter traffic of the whole solve (per fused launch: the matrix once, u read
-once, w and x read and written) divided by the solve's wall time.  The
-`roofline` object times the fused kernel alone with HIP events on the
-library's stream.  Prints one JSON line.
+Headline (the largest single-GPU lattice, 256x256x64, N = 16,777,216, 128
+search vectors in complex128, SELL-32-256): a step is one fused launch of
+the Chebyshev filter (Fig. fig:ChebFD: the sparse matrix-multiple-vector
+product fused with the three-term recurrence and the filter accumulation,
+Sec. 4), with the matrix and the three blocks resident in HBM.  The timed
+region is one filter application of degree K, i.e. exactly K fused launches
+(the first two set up the recurrence); `value` is their algorithmic bytes
+(the matrix once, u read once, w and x read and written, per launch)
+divided by the region's wall time.  The `roofline` object gives the plain
+recurrence launch alone: its HIP-event duration is the difference of the
+degree-K and degree-2 applications over K - 2, on the library's stream.
+A complete solve at this size takes 700-1000 s, so time to all window
+eigenpairs is reported from the 128x128x64 lattice (precision form and FP64
+form on Lanczos bounds) and the 64x64x32 lattice (FP64).  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -22,6 +28,7 @@ import hashlib
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -34,7 +41,8 @@ import chebfd_inputs as inp  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = {"sell": ["kernels_step.hip", "pack.h", "dispatch.h", "matrix.cpp"],
-                  "stencil": ["kernels_stencil.hip", "pack.h", "dispatch.h"]}
+                  "stencil": ["kernels_stencil.hip", "pack.h", "dispatch.h", "matrix.cpp"]}
+METRIC = "fused Chebyshev SpMMV GB/s vs HBM peak; time to all window eigenpairs @res<1e-9"
 
 
 def source_sha(storage):
@@ -65,88 +73,163 @@ def measured_traffic(storage, precision, workload):
     return t
 
 
-def cpu_baseline(workload, target_s=15.0, max_steps=400):
-    """The CPU reference's filter (plain CSR, OpenMP static over the host
-    threads) on the same lattice and block width, timed on the host cores.
-    The number of recurrence steps is chosen from a two-step probe so that
-    the timed sample takes about target_s seconds."""
+def host_info():
+    model, mem = platform.processor() or "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return model, mem
+
+
+def cpu_baseline(L, n_s, target_s=15.0, max_steps=400):
+    """The oracle's filter (plain CSR, OpenMP static over the host threads)
+    on an 8-layer slab of the lattice (same x-y extent and block width as
+    the GPU figure; the full lattice's blocks do not fit host memory), timed
+    on the host cores.  The number of recurrence steps is chosen from a
+    two-step probe so that the timed sample takes about target_s seconds."""
     import oracle
-    w = inp.WORKLOADS[workload]
-    L = w["L"]
-    H = oracle.ti_hamiltonian(*L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0])
+    Ls = (L[0], L[1], min(L[2], 8))
+    H = oracle.ti_hamiltonian(*Ls, pbc=3, V=1.0, seed=1)
     a, b = oracle.gershgorin(H)
-    n_s = w["n_s"]
     X = inp.random_block(H.n, n_s, seed=1)
+    d = 0.02 * max(abs(a), abs(b))
     t0 = time.perf_counter()
-    oracle.filter_block(H, a, b, oracle.gamma(-w["delta"], w["delta"], a, b, 2), X)
+    oracle.filter_block(H, a, b, oracle.gamma(-d, d, a, b, 2), X)
     per_step = (time.perf_counter() - t0) / 2
     n_steps = int(min(max_steps, max(3, target_s / max(per_step, 1e-6))))
-    gam = oracle.gamma(-w["delta"], w["delta"], a, b, n_steps)
+    gam = oracle.gamma(-d, d, a, b, n_steps)
     t0 = time.perf_counter()
     oracle.filter_block(H, a, b, gam, X)
     dt = time.perf_counter() - t0
     vb = H.nnz * 20 + 5 * H.n * n_s * 16
+    model, mem = host_info()
     return dict(value=round(n_steps * vb / dt / 1e9, 3), unit="GB/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"filter of degree {n_steps} ({n_steps} fused recurrence steps of Fig. "
-                       f"fig:ChebFD, CSR, OpenMP static) on the full {L[0]}x{L[1]}x{L[2]} lattice, "
-                       f"n_s={n_s}, c128, {dt:.1f} s on {oracle.num_threads()} threads; same "
-                       f"per-step byte count as the GPU figure")
+                kind="oracle", cpu_model=model, host_mem_gib=mem,
+                sample=f"filter of degree {n_steps} ({n_steps} recurrence steps of Fig. "
+                       f"fig:ChebFD, CSR, OpenMP static) on the {Ls[0]}x{Ls[1]}x{Ls[2]} slab of "
+                       f"the lattice (N={H.n}), n_s={n_s}, c128, {dt:.1f} s on "
+                       f"{oracle.num_threads()} threads; bytes per step nnz*20 + 5*N*n_s*16, "
+                       f"as for the GPU figure")
 
 
-def time_fused(B, ctx, H, prec, n_s, delta, steps):
-    """Average duration of one fused MODE_STEP launch, from HIP events
-    recorded on the library's stream around `steps` launches."""
-    import torch
-    info = H.info()
-    a, b = info["g_lo"], info["g_hi"]
-    dt = torch.complex128 if prec == B.PREC_C128 else torch.complex64
-    X = torch.empty((info["n"], n_s), dtype=dt, device="cuda")
-    U = torch.empty_like(X)
-    W = torch.empty_like(X)
-    B.chebfd_random_block(ctx, X, seed=7)
-    gam = B.chebfd_coeffs(-delta, delta, a, b, steps)
-    B.chebfd_filter_apply(ctx, H, gam[:3], a, b, X, U, W)   # warm-up
+def launch_bytes(mat, n, n_s, s_d, k):
+    """Algorithmic bytes of a degree-k filter application: the first launch
+    reads u and writes w, the second reads u and x and writes w and x, each
+    later one reads u, w, x and writes w, x; every launch reads the matrix."""
+    blk = n * n_s * s_d
+    return k * mat + blk * (2 + 4 + 5 * (k - 2))
+
+
+class Blocks:
+    """The three device blocks of the filter, allocated once per precision."""
+
+    def __init__(self, torch, B, ctx, n, n_s, prec):
+        dt = torch.complex128 if prec == B.PREC_C128 else torch.complex64
+        self.X = torch.empty((n, n_s), dtype=dt, device="cuda")
+        self.U = torch.empty_like(self.X)
+        self.W = torch.empty_like(self.X)
+        B.chebfd_random_block(ctx, self.X, seed=7)
+
+
+def time_filter(torch, B, ctx, H, blocks, gam, a, b):
+    """HIP-event and wall time of one filter application on the library's
+    stream (the context runs on torch's current stream)."""
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ev0.record(stream)
-    B.chebfd_filter_apply(ctx, H, gam, a, b, X, U, W)
-    ev1.record(stream)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    B.chebfd_filter_apply(ctx, H, gam, a, b, blocks.X, blocks.U, blocks.W)
+    e1.record(stream)
     torch.cuda.synchronize()
-    del X, U, W
+    return e0.elapsed_time(e1) / 1e3, time.perf_counter() - w0
+
+
+def step_time(torch, B, ctx, H, blocks, a, b, k):
+    """Average duration of one plain recurrence launch: (t(degree k) -
+    t(degree 2)) / (k - 2), the degree-2 time the median of three."""
+    d = 0.02 * max(abs(a), abs(b))
+    gk = B.chebfd_coeffs(-d, d, a, b, k)
+    time_filter(torch, B, ctx, H, blocks, gk[:3].copy(), a, b)   # warm-up
+    tk = time_filter(torch, B, ctx, H, blocks, gk, a, b)[0]
+    t2 = sorted(time_filter(torch, B, ctx, H, blocks, gk[:3].copy(), a, b)[0] for _ in range(3))
+    return (tk - t2[1]) / (k - 2)
+
+
+def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
+    """One complete solve (Sec. 3.1 steps 1-8) on a lattice with its window
+    from the workload table; returns a summary dict and the eigenvalues."""
+    w = inp.WORKLOADS[wname]
+    st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    H = B.Matrix.ti(ctx, w["L"], pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st,
+                    sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
+    info = H.info()
+    steps = 40 if bounds == "lanczos" else 0
+    a, b = (B.chebfd_lanczos_bounds(ctx, H, k=40, seed=w["seeds"][0]) if steps
+            else (info["g_lo"], info["g_hi"]))
+    d = w["delta"]
+    dp = d * (math.sqrt(w["n_s"] / w["n_target"]) - 1.0)
+    n_p, eta = B.chebfd_optimal_np(a, b, -d, d, -d - dp, d + dp)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=w["n_s"], n_p=n_p, kernel=w["kernel"],
+                         mu=w["mu"], eps=w["eps"], max_iter=60, precision=prec, lock=1,
+                         seed=w["seeds"][0], vectors=0, bounds=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, ev, rs, _, stats = B.chebfd_solve(ctx, H, p)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    del H
     torch.cuda.empty_cache()
-    return ev0.elapsed_time(ev1) / 1e3 / steps
+    out = {"workload": wname, "storage": storage,
+           "precision": "c128" if prec == B.PREC_C128 else "c64 sweep + c128 polish",
+           "bounds": [round(a, 4), round(b, 4), bounds], "window": [-d, d], "n_s": w["n_s"],
+           "n_p": n_p, "time_to_solution_s": round(T, 3), "status": int(rc),
+           "eigenpairs_found": int(ev.size), "max_residual": float(rs.max()) if rs.size else None,
+           "iterations": stats["iterations"], "iterations_c64": stats["iterations_c64"],
+           "n_mvm": stats["n_mvm"], "t_filter_s": round(stats["t_filter"], 3),
+           "t_ortho_s": round(stats["t_ortho"], 3), "t_rr_s": round(stats["t_rr"], 3)}
+    if prec != B.PREC_C128 and stats["sweep_evals"].size:
+        out["sweep_pairs"] = int(stats["sweep_evals"].size)
+        out["sweep_max_residual"] = float(stats["sweep_residuals"].max())
+    print(f"# solve {tag}: {T:.2f} s, {ev.size} pairs, max residual "
+          f"{out['max_residual']}", flush=True)
+    return out, ev
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ti_64x64x32")
+    ap.add_argument("--steps", type=int, default=40,
+                    help="fused launches in the timed region (one filter of this degree)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed fused launches first")
+    ap.add_argument("--workload", default="ti_256x256x64")
     ap.add_argument("--storage", default="sell", choices=["sell", "stencil"])
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="only the bandwidth probe and the timed fused launches")
-    ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
-                    help="spectral interval for the scaling: Gershgorin (default) or 40 "
-                         "Lanczos steps, checked by the solver")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-lanczos", action="store_true",
-                    help="skip the extra solve on Lanczos bounds")
-    ap.add_argument("--no-other-storage", action="store_true",
-                    help="skip the fused-kernel timing (and solve) of the other storage")
     ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1],
-                    help="block order of the fused step (tuning key 'order'): -1 automatic, "
-                         "0 column-slab major, 1 tiled lattice order (matrix-free lattice)")
-    ap.add_argument("--kernel-steps", type=int, default=100,
-                    help="fused launches timed with HIP events for the roofline figure")
+                    help="block order of the matrix-free step (tuning key 'order'): -1 "
+                         "automatic, 0 column-slab major, 1 tiled lattice order")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the bandwidth probe and the timed fused launches (no solves)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the other storage and the other precision's kernel timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding across GPUs "
               "is designed but not built", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 3:
+        sys.exit("bench.py: --steps must be >= 3")
 
     import torch
     from paper_1510_04895_amd import binding as B
@@ -157,9 +240,7 @@ def main():
     ctx = B.Context(0)
     if args.order != -1:
         B.chebfd_set_tuning(ctx, "order", args.order)
-    stream = torch.cuda.current_stream()
     prec = B.PREC_C128 if args.precision == "c128" else B.PREC_C64
-    s_d = 16 if prec == B.PREC_C128 else 8
 
     # attainable bandwidth (read-only reduction, copy, 3-read/2-write stream)
     buf = torch.empty(4 * 2**30, dtype=torch.uint8, device="cuda")
@@ -168,155 +249,122 @@ def main():
     torch.cuda.empty_cache()
     print(f"# probe GB/s read {probe[0]:.0f} copy {probe[1]:.0f} 3r2w {probe[2]:.0f}", flush=True)
 
-    st = B.STORAGE_SELL if args.storage == "sell" else B.STORAGE_STENCIL
-    t0 = time.perf_counter()
-    H = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st,
-                    sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
-    t_build = time.perf_counter() - t0
-    info = H.info()
+    mats, kern = {}, {}
+    for storage in [args.storage] + ([] if args.no_other else
+                                     [s for s in ("sell", "stencil") if s != args.storage]):
+        st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+        t0 = time.perf_counter()
+        mats[storage] = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0],
+                                    storage=st, sell_C=w.get("sell_C", 32),
+                                    sell_sigma=w.get("sell_sigma", 256))
+        print(f"# matrix {storage} built in {time.perf_counter() - t0:.2f} s", flush=True)
+    info = mats[args.storage].info()
     n, nnz = info["n"], info["nnz"]
     a, b = info["g_lo"], info["g_hi"]
-    lanczos_steps = 0
-    if args.bounds == "lanczos":
-        # the same estimate the solver makes (same seed and steps)
-        lanczos_steps = 40
-        a, b = B.chebfd_lanczos_bounds(ctx, H, k=lanczos_steps, seed=w["seeds"][0])
-    mat_bytes = info["matrix_bytes_c128"] if prec == B.PREC_C128 else info["matrix_bytes_c64"]
-    vb = mat_bytes + 5 * n * n_s * s_d              # algorithmic bytes per fused launch
-    print(f"# matrix {args.storage} N={n} nnz={nnz} built in {t_build:.2f} s", flush=True)
 
-    # window and filter degree (linear DOS near the centre: delta'/delta =
-    # sqrt(N_S/N_T) - 1, Sec. 2.4; eta-minimising N_p, Sec. 2.3)
-    delta = w.get("delta")
-    if delta is not None:
-        dp = delta * (math.sqrt(n_s / w["n_target"]) - 1.0)
-        n_p, eta = B.chebfd_optimal_np(a, b, -delta, delta, -delta - dp, delta + dp)
-    elif args.kernel_only:
-        # the larger lattices take their window from the KPM count (their
-        # solves run through paper_1510_04895_amd.scale_runs); the timed
-        # launches need coefficients only
-        delta, n_p, eta = 0.02 * max(abs(a), abs(b)), None, None
-    else:
-        sys.exit(f"bench.py: {args.workload} has no fixed window; solve it with "
-                 "python -m paper_1510_04895_amd.scale_runs, or time its kernel with --kernel-only")
+    def mat_bytes(storage, p):
+        i = mats[storage].info()
+        return i["matrix_bytes_c128"] if p == B.PREC_C128 else i["matrix_bytes_c64"]
 
-    # --- the fused kernel alone, timed with HIP events on the library stream
-    ks = args.kernel_steps
-    t_launch = time_fused(B, ctx, H, prec, n_s, delta, ks)
-    kern_gbs = vb / t_launch / 1e9
-    print(f"# fused launch {t_launch * 1e6:.1f} us = {kern_gbs:.0f} GB/s", flush=True)
+    precs = [prec] + ([] if args.no_other else
+                      [B.PREC_C64 if prec == B.PREC_C128 else B.PREC_C128])
+    headline = None
+    for pr in precs:
+        s_d = 16 if pr == B.PREC_C128 else 8
+        blocks = Blocks(torch, B, ctx, n, n_s, pr)
+        for storage in mats:
+            H = mats[storage]
+            vstep = mat_bytes(storage, pr) + 5 * n * n_s * s_d
+            if storage == args.storage and pr == prec:
+                d = 0.02 * max(abs(a), abs(b))
+                # warm-up, then exactly K fused launches (one filter of degree K)
+                time_filter(torch, B, ctx, H, blocks,
+                            B.chebfd_coeffs(-d, d, a, b, max(args.warmup, 2)), a, b)
+                gk = B.chebfd_coeffs(-d, d, a, b, args.steps)
+                t_ev, t_wall = time_filter(torch, B, ctx, H, blocks, gk, a, b)
+                t2 = sorted(time_filter(torch, B, ctx, H, blocks, gk[:3].copy(), a, b)[0]
+                            for _ in range(3))
+                t_step = (t_ev - t2[1]) / (args.steps - 2)
+                headline = dict(t_wall=t_wall, t_ev=t_ev, t_step=t_step, vstep=vstep,
+                                vk=launch_bytes(mat_bytes(storage, pr), n, n_s, s_d, args.steps))
+            else:
+                t_step = step_time(torch, B, ctx, H, blocks, a, b, 22)
+            key = f"{storage}_{'c128' if pr == B.PREC_C128 else 'c64'}"
+            kern[key] = {"avg_launch_us": round(t_step * 1e6, 2),
+                         "algorithmic_bytes_per_launch": int(vstep),
+                         "achieved_gbs": round(vstep / t_step / 1e9, 1),
+                         "frac": round(vstep / t_step / 1e9 / HBM_PEAK_GBS, 4)}
+            print(f"# {key}: fused launch {t_step * 1e6:.1f} us = {vstep / t_step / 1e9:.0f} "
+                  f"GB/s", flush=True)
+        del blocks
+        torch.cuda.empty_cache()
+    mats.clear()
+    torch.cuda.empty_cache()
 
     traffic = measured_traffic(args.storage, args.precision, args.workload)
-    roof = {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kern_gbs / HBM_PEAK_GBS, 4),
+    t_step = headline["t_step"]
+    roof = {"bound": "hbm", "achieved": round(headline["vstep"] / t_step / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(headline["vstep"] / t_step / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": (int(traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None),
-            "algorithmic_bytes_per_launch": int(vb), "avg_launch_us": round(t_launch * 1e6, 2),
-            "frac_of_probe_3r2w": round(kern_gbs / probe[2], 4)}
-    out = {
-        "metric": "fused Chebyshev SpMMV GB/s vs HBM peak; time to all window eigenpairs @res<1e-9",
-        "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == B.PREC_C128 else "f32 sweep + f64 polish",
-        "data": "synthetic",
-    }
-    cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "n_s": n_s,
-           "n_p": n_p, "eta": None if eta is None else round(eta, 2), "kernel": w["kernel"],
-           "window": [-delta, delta], "order": args.order,
-           "storage": args.storage, "bounds": [round(a, 4), round(b, 4), args.bounds],
-           "sell_C_sigma": [w.get("sell_C"), w.get("sell_sigma")] if args.storage == "sell" else None,
-           "eps": w["eps"]}
+            "kernel": ("k_step_sell" if args.storage == "sell" else "k_step_ti") + " (MODE_STEP)",
+            "algorithmic_bytes_per_launch": int(headline["vstep"]),
+            "avg_launch_us": round(t_step * 1e6, 2),
+            "frac_of_probe_3r2w": round(headline["vstep"] / t_step / 1e9 / probe[2], 4)}
+    cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "nnz": nnz,
+           "n_s": n_s, "storage": args.storage, "order": args.order,
+           "sell_C_sigma": [w.get("sell_C", 32), w.get("sell_sigma", 256)]
+           if args.storage == "sell" else None,
+           "step": "one fused Chebyshev launch (spMMV + recurrence + accumulation)",
+           "bounds": [round(a, 4), round(b, 4), "gershgorin"]}
+    out = {"metric": METRIC, "value": round(headline["vk"] / headline["t_wall"] / 1e9, 2),
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(headline["t_wall"] / args.steps * 1e3, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == B.PREC_C128 else "f32", "data": "synthetic",
+           "config": cfg,
+           "timed_region_event_s": round(headline["t_ev"], 5),
+           "fused_kernel_tflops": round(step_flops(n, n_s, nnz / n) / t_step / 1e12, 3),
+           "kernels": kern,
+           # the paper's own filter-step rate on a CPU cluster (Table
+           # tab:benchmark, largest TI run): another machine and a 64x larger
+           # matrix, so context for the flop/s figure, not a target
+           "paper_context": {"value": 43.9, "unit": "Tflop/s", "per_node": 0.0857,
+                             "system": "512 CPU nodes, two 14-core Xeon E5-2697v3 each",
+                             "workload": "TI matrix, D = 1.07e9, N_S = 256, N_p = 8639",
+                             "flop_convention": "same complex counting (Sec. 4.2)"}}
 
-    if args.kernel_only:
-        out.update({"value": round(kern_gbs, 2), "steps": 0, "warmup": 0,
-                    "ms_per_step": round(t_launch * 1e3, 4), "config": cfg,
-                    "note": "kernel only: value is the fused launch's algorithmic GB/s"})
-    else:
-        params = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p,
-                                  kernel=w["kernel"], mu=w["mu"], eps=w["eps"], max_iter=60,
-                                  precision=prec, lock=1, seed=w["seeds"][0], vectors=0,
-                                  bounds=lanczos_steps)
-        for _ in range(args.warmup):
-            B.chebfd_solve(ctx, H, params)
-        torch.cuda.synchronize()
-        times, res = [], None
-        for k in range(args.steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = B.chebfd_solve(ctx, H, params)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-            print(f"# solve {k}: {times[-1]:.3f} s, {len(res[1])} pairs", flush=True)
-        T = float(np.mean(times))
-        rc, ev, rs, _, stats = res
-        solve_bytes = stats["n_mvm"] / n_s * vb     # sum over launches of algorithmic bytes
-        nnz_row = nnz / n
-        out.update({
-            "value": round(solve_bytes / T / 1e9, 2), "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(T * 1e3, 2), "config": cfg,
-            "time_to_solution_s": round(T, 4), "eigenpairs_found": int(len(ev)),
-            "max_residual": float(rs.max()) if len(rs) else None, "status": int(rc),
-            "solve_stats": {k: (round(v, 4) if isinstance(v, float) else v)
-                            for k, v in stats.items()},
-            "fused_kernel_tflops": round(step_flops(n, n_s, nnz_row) / t_launch / 1e12, 3),
-            # the paper's own filter-step rate on a CPU cluster (Table
-            # tab:benchmark, largest TI run): another machine and a 2000x
-            # larger matrix, so context for the flop/s figure, not a target
-            "paper_context": {"value": 43.9, "unit": "Tflop/s", "per_node": 0.0857,
-                              "system": "512 CPU nodes, two 14-core Xeon E5-2697v3 each",
-                              "workload": "TI matrix, D = 1.07e9, N_S = 256, N_p = 8639",
-                              "flop_convention": "same complex counting (Sec. 4.2)"},
-        })
-    # the same solve on Lanczos bounds instead of Gershgorin's (Sec. 3.1
-    # step 1): same eigenpairs, a ~1.5x lower filter degree
-    if not args.kernel_only and args.bounds == "gershgorin" and not args.no_lanczos:
-        al, bl = B.chebfd_lanczos_bounds(ctx, H, k=40, seed=w["seeds"][0])
-        n_pl, _ = B.chebfd_optimal_np(al, bl, -delta, delta, -delta - dp, delta + dp)
-        pl = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_pl,
-                              kernel=w["kernel"], mu=w["mu"], eps=w["eps"], max_iter=60,
-                              precision=prec, lock=1, seed=w["seeds"][0], vectors=0, bounds=40)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rl = B.chebfd_solve(ctx, H, pl)
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t0
-        out["lanczos_bounds"] = {
-            "bounds": [round(al, 4), round(bl, 4)], "n_p": n_pl, "time_to_solution_s": round(tl, 4),
-            "eigenpairs_found": int(len(rl[1])),
-            "max_residual": float(rl[2].max()) if len(rl[2]) else None,
-            "same_eigenvalues": bool(len(rl[1]) == len(res[1]) and (
-                len(rl[1]) == 0 or np.abs(rl[1] - res[1]).max() < 1e-10 * max(abs(a), abs(b))))}
-        print(f"# lanczos bounds [{al:.3f}, {bl:.3f}]: n_p {n_pl}, solve {tl:.3f} s", flush=True)
-    # the other storage of the same lattice: matrix-free stencil (or SELL)
-    if not args.no_other_storage:
-        other = "stencil" if args.storage == "sell" else "sell"
-        Ho = B.Matrix.ti(ctx, L, pbc=w["pbc"], V=w["V"], seed=w["seeds"][0],
-                         storage=B.STORAGE_STENCIL if other == "stencil" else B.STORAGE_SELL,
-                         sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
-        io = Ho.info()
-        mbo = io["matrix_bytes_c128"] if prec == B.PREC_C128 else io["matrix_bytes_c64"]
-        vbo = mbo + 5 * n * n_s * s_d
-        to = time_fused(B, ctx, Ho, prec, n_s, delta, ks)
-        extra = {"storage": other, "algorithmic_bytes_per_launch": int(vbo),
-                 "avg_launch_us": round(to * 1e6, 2), "achieved_gbs": round(vbo / to / 1e9, 1),
-                 "frac": round(vbo / to / 1e9 / HBM_PEAK_GBS, 4)}
-        if not args.kernel_only:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r2 = B.chebfd_solve(ctx, Ho, params)
-            torch.cuda.synchronize()
-            extra["time_to_solution_s"] = round(time.perf_counter() - t0, 4)
-            extra["eigenpairs_found"] = int(len(r2[1]))
-            extra["max_residual"] = float(r2[2].max()) if len(r2[2]) else None
-            extra["same_eigenvalues"] = bool(len(r2[1]) == len(res[1]) and (
-                len(r2[1]) == 0 or np.abs(r2[1] - res[1]).max() < 1e-10 * max(abs(a), abs(b))))
-        out["other_storage"] = extra
-        del Ho
-        print(f"# {other}: fused launch {to * 1e6:.1f} us = {vbo / to / 1e9:.0f} GB/s", flush=True)
+    if not args.kernel_only:
+        # time to all window eigenpairs: the precision form against the FP64
+        # form at 128x128x64 (Lanczos bounds), and the FP64 solve at 64x64x32
+        tts = {}
+        r64, ev64 = solve_case(torch, B, ctx, "ti_128x128x64", args.storage, B.PREC_C128,
+                               "lanczos", "128x128x64 c128")
+        r32, ev32 = solve_case(torch, B, ctx, "ti_128x128x64", args.storage, B.PREC_C64,
+                               "lanczos", "128x128x64 c64")
+        S_w = max(abs(r64["bounds"][0]), abs(r64["bounds"][1]))
+        r32["same_eigenvalues_as_fp64"] = bool(
+            ev32.size == ev64.size and (ev64.size == 0 or
+                                        np.abs(ev32 - ev64).max() < 1e-10 * S_w))
+        r32["speedup_over_fp64"] = round(r64["time_to_solution_s"] / r32["time_to_solution_s"], 3)
+        tts["ti_128x128x64_fp64"] = r64
+        tts["ti_128x128x64_precision_form"] = r32
+        r2, ev2 = solve_case(torch, B, ctx, "ti_64x64x32", args.storage, B.PREC_C128,
+                             "gershgorin", "64x64x32 c128")
+        gold = os.path.join(ROOT, "tests", "golden", "ti_64x64x32_V1_seed1_window0.23.txt")
+        if os.path.exists(gold):
+            g = np.sort(np.loadtxt(gold)[:, 0])
+            g = g[np.abs(g) <= r2["window"][1]]
+            S2 = max(abs(r2["bounds"][0]), abs(r2["bounds"][1]))
+            r2["matches_oracle_window"] = bool(g.size == ev2.size and
+                                               np.abs(g - ev2).max() < 1e-10 * S2)
+        tts["ti_64x64x32_fp64"] = r2
+        out["time_to_solution"] = tts
     out["roofline"] = roof
     out["bandwidth_probe_gbs"] = {"read_only": round(probe[0], 1), "copy": round(probe[1], 1),
                                   "stream_3r2w": round(probe[2], 1)}
-    out["matrix_build_s"] = round(t_build, 2)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(L, n_s)
     print(json.dumps(out), flush=True)
 
 

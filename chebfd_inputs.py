@@ -23,7 +23,7 @@ WORKLOADS = {
                         mu=2.0, eps=1e-9, n_target=64, delta=0.2072, sell_C=32, sell_sigma=256),
     # precision form
     "ti_128x128x64": dict(L=(128, 128, 64), pbc=3, V=1.0, seeds=(1,), n_s=256,
-                          kernel="lanczos", mu=2.0, eps=1e-9, n_target=100),
+                          kernel="lanczos", mu=2.0, eps=1e-9, n_target=100, delta=0.1335),
     # learned form: disorder strength per realisation W ~ U[0,2]
     "ti_32x32x16": dict(L=(32, 32, 16), pbc=3, train_seeds=tuple(range(1, 201)),
                         heldout_seeds=tuple(range(10001, 10021)), n_kpm_vec=8, n_kpm_mom=256),

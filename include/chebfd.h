@@ -252,7 +252,8 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *                 (strips of "tile" x-columns, z fastest inside a column,
  *                 one strip per XCD group);
  *   "tile"        strip width of the tiled lattice order, in sites along x:
- *                 -1 (default) = 4, used where the tiled order pays (above);
+ *                 -1 (default) = 4 for the matrix-free step, 2 for SELL,
+ *                 used where the tiled order pays (above);
  *                 a positive value also makes every SELL matrix built by
  *                 chebfd_matrix_ti on this context take the tiled row order
  *                 (the chunk composition of SELL-C-sigma); 0 = never tiled;
@@ -260,6 +261,19 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
  *                 each chunk, rows whose entries gather the same columns at
  *                 the same positions are placed in adjacent slots (one wave
  *                 instruction), 0 = length-sorted order only;
+ *   "slabs"       SELL only: column slabs (32 lanes x 16 bytes) a workgroup
+ *                 runs on one staging of its row block's index and value
+ *                 stream; 0 (default) = all slabs of the block, so the
+ *                 matrix is read from memory once per launch;
+ *   "row_group"   SELL matrices built on this context: -1 (default) = the
+ *                 row-group layout where it saves at least a quarter of the
+ *                 gathers, trying groups of 4 rows, then 2 (each group of
+ *                 consecutive slots stores the union of its rows' columns
+ *                 once with one value per row and entry, and one lane
+ *                 applies every gathered row to all rows of its group);
+ *                 2 or 4 = that group size whenever every union fits the
+ *                 32-entry LDS stage; 1 = one row per slot (plain
+ *                 SELL-C-sigma);
  *   "xcd_group"   consecutive workgroups placed on one of the 8 XCDs (each
  *                 with its own L2): 1 = hardware round-robin order, a power
  *                 of two up to 2^20, 0 = default (the workgroups of one SELL
@@ -485,6 +499,14 @@ int chebfd_solve(chebfd_ctx *ctx, const chebfd_matrix *H, const chebfd_params *p
 int chebfd_result_get(const chebfd_result *r, int64_t *n_found, const double **evals,
                       const double **residuals, const double **evecs, chebfd_stats *stats);
 int chebfd_result_destroy(chebfd_result *r);
+
+/* Precision form (CHEBFD_PREC_C64): the result of the complex64 sweep
+ * before the FP64 polish -- the in-window Ritz values of its last iteration
+ * (Rayleigh-Ritz in FP64 on the FP32-filtered block) whose residual
+ * ||Hv - theta v|| was at most sqrt(eps), ascending, with those residuals.
+ * n = 0 for complex128 solves.  Pointers into the result, owned by it. */
+int chebfd_result_sweep(const chebfd_result *r, int64_t *n, const double **evals,
+                        const double **residuals);
 
 #ifdef __cplusplus
 }

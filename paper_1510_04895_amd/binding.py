@@ -88,6 +88,7 @@ def lib():
         "chebfd_kpm_moments": (i32, [vp, vp, i32, i32, i32, u64, dbl, dbl, vp]),
         "chebfd_host_eigh": (i32, [i32, vp, vp]),
         "chebfd_set_tuning": (i32, [vp, C.c_char_p, i32]),
+        "chebfd_result_sweep": (i32, [vp, vp, vp, vp]),
         "chebfd_bandwidth_probe": (i32, [vp, vp, i64, i32, vp]),
         "chebfd_dos_params": (i32, [vp, i32, i64, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, vp,
                                     vp, vp, vp]),
@@ -132,7 +133,7 @@ def exported_symbols():
                         "chebfd_gram chebfd_block_times chebfd_residual_norms "
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
                         "chebfd_params_default chebfd_solve_workspace_size chebfd_solve "
-                        "chebfd_result_get chebfd_result_destroy chebfd_set_tuning "
+                        "chebfd_result_get chebfd_result_sweep chebfd_result_destroy chebfd_set_tuning "
                         "chebfd_bandwidth_probe chebfd_dos_params chebfd_learned_features "
                         "chebfd_learned_decode chebfd_fit_corrections chebfd_mlp_create "
                         "chebfd_mlp_destroy chebfd_mlp_num_params chebfd_mlp_get_params "
@@ -537,7 +538,14 @@ def chebfd_solve(ctx, H, params: Params):
         if k and bool(vv):
             N = H.info()["n"]
             vecs = np.ctypeslib.as_array(vv, (N * k * 2,)).copy().view(np.complex128).reshape(N, k)
-        return rc, evals, resid, vecs, st.as_dict()
+        stats = st.as_dict()
+        # the complex64 sweep's in-window pairs before the FP64 polish
+        ns_ = C.c_int64()
+        _check(lib().chebfd_result_sweep(res, C.byref(ns_), C.byref(ev), C.byref(rs)))
+        m = ns_.value
+        stats["sweep_evals"] = np.ctypeslib.as_array(ev, (m,)).copy() if m else np.empty(0)
+        stats["sweep_residuals"] = np.ctypeslib.as_array(rs, (m,)).copy() if m else np.empty(0)
+        return rc, evals, resid, vecs, stats
     finally:
         lib().chebfd_result_destroy(res)
         del ws

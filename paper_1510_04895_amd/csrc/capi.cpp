@@ -370,6 +370,9 @@ int chebfd_set_tuning(chebfd_ctx *ctx, const char *key, int value)
     else if (k == "order" && value >= -1 && value <= 1) ctx->tune_order = value;
     else if (k == "tile" && value >= -1 && value <= 256) ctx->tune_tile = value;
     else if (k == "pair_rows" && (value == 0 || value == 1)) ctx->tune_pair_rows = value;
+    else if (k == "slabs" && value >= 0 && value <= 64) ctx->tune_slabs = value;
+    else if (k == "row_group" && (value == -1 || value == 1 || value == 2 || value == 4))
+        ctx->tune_row_group = value;
     else if (k == "xcd_group" && value >= 0 && value <= (1 << 20) && !(value & (value - 1)))
         ctx->tune_xcd_group = value;
     else return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_set_tuning: unknown key or value");

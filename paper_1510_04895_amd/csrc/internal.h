@@ -32,6 +32,11 @@ int fail(int code, const std::string &msg);
     } while (0)
 
 // ---------------------------------------------------------------- handles
+// Entries per row (or row pair) the SELL kernels stage in LDS; longer rows
+// read the index stream directly (single rows) or keep the plain layout
+// (pairs).
+constexpr int kStageLen = 32;
+
 struct Sell {
     int64_t n = 0;           // rows
     int C = 32;              // chunk height
@@ -47,6 +52,13 @@ struct Sell {
     int32_t *col = nullptr;         // stored
     double *val64 = nullptr;        // stored complex128 (interleaved)
     float *val32 = nullptr;         // stored complex64
+    // Row groups (group = G > 1): slots G q .. G q + G - 1 of a chunk form
+    // group q (C/G groups per chunk); a group stores the union of its rows'
+    // columns once, with G values per entry (zero where a row has no
+    // entry), entry j of group q at chunk_ptr[c] + j*C/G + q; val64/val32
+    // then hold G complex values per stored entry and chunk_len is the
+    // widest union of the chunk.  group = 1: plain SELL-C-sigma.
+    int group = 1;
     // rows per locality group of the chunk order (one strip of a tiled
     // lattice numbering; 0 = none): the workgroups of one group share an XCD
     int64_t group_rows = 0;
@@ -76,6 +88,8 @@ struct chebfd_ctx {
     int tune_nt = 1;      // non-temporal hint on the streamed blocks w, x
     int tune_order = -1;  // matrix-free step: -1 automatic, 0 slab-major, 1 tiled lattice order
     int tune_pair_rows = 1; // SELL build: pair rows with equal gather columns in a chunk
+    int tune_slabs = 0;     // SELL: column slabs per workgroup (0 = default)
+    int tune_row_group = -1; // SELL build: row-group layout, -1 where it pays, 2/4 whenever it fits, 1 never
     int tune_xcd_group = 0; // consecutive workgroups per XCD: 0 = default, 1 = hardware order
     int tune_tile = -1;     // strip width (sites along x) of the tiled lattice order: -1 default, 0 off
 };
@@ -92,7 +106,7 @@ struct chebfd_matrix {
 namespace chebfd {
 
 // scratch management (grows on demand; synchronises the stream before growing)
-int default_tile(const chebfd_ctx *ctx);
+int default_tile(const chebfd_ctx *ctx, bool sell);
 bool tiled_order_pays(const int L[3], int64_t slab_row);
 int ensure_scratch(chebfd_ctx *ctx, size_t bytes);
 int ensure_pinned(chebfd_ctx *ctx, size_t bytes);

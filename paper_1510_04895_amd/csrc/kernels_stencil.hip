@@ -302,7 +302,7 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
     int order = ctx->tune_order >= 0 ? ctx->tune_order : auto_order<T, SW>(S, a.n_s);
     // tiled order: the largest strip width up to the default that divides Lx
-    int tile = std::min(default_tile(ctx), S.L[0]);
+    int tile = std::min(default_tile(ctx, false), S.L[0]);
     while (tile > 1 && S.L[0] % tile) --tile;
     if (order == 1 && tile < 1) order = 0;
     const int64_t nzb = (S.L[2] + SPB - 1) / SPB;

@@ -57,6 +57,25 @@ __device__ __forceinline__ void store_value(T *p, T re, T im)
     *reinterpret_cast<typename CVal<T>::V *>(p) = v;
 }
 
+// acc += h * g for complex h, g, as four fused multiply-adds in a fixed
+// order, so that every SELL layout computes each row's sum with the same
+// operations (an entry with h = 0 leaves acc unchanged).
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c)
+{
+    if constexpr (std::is_same<T, double>::value) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+template <typename T>
+__device__ __forceinline__ void cmac(T &ar, T &ai, T hr, T hi, T gr, T gi)
+{
+    ar = fmadd<T>(hr, gr, ar);
+    ar = fmadd<T>(-hi, gi, ar);
+    ai = fmadd<T>(hr, gi, ai);
+    ai = fmadd<T>(hi, gr, ai);
+}
+
 // Block row r of a row-major block as a byte offset from the lane's column
 // base: one 32x32->64-bit multiply-add per gather (row_bytes = ld * entry
 // size, checked on the host to fit 32 bits).
@@ -66,7 +85,7 @@ __device__ __forceinline__ const T *row_at(const char *ub, uint32_t r, uint32_t 
     return reinterpret_cast<const T *>(ub + (uint64_t)r * row_bytes);
 }
 
-constexpr int LS = 32;   // staged entries per row; longer rows read the stream directly
+constexpr int LS = kStageLen;   // staged entries per row; longer rows read the stream directly
 
 // Accumulates one row of the sparse product from the LDS stage.  The stage
 // keeps the SELL order (entry j of block row q at j*RPP + q) and pads every
@@ -105,10 +124,7 @@ __device__ __forceinline__ void row_product_staged(const char *ub, uint32_t row_
             T hr, hi;
             load_value<T>(sval, (int64_t)(j + i) * RPP, hr, hi);
 #pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                ar[e] += hr * g[i].re[e] - hi * g[i].im[e];
-                ai[e] += hr * g[i].im[e] + hi * g[i].re[e];
-            }
+            for (int e = 0; e < NB; ++e) cmac<T>(ar[e], ai[e], hr, hi, g[i].re[e], g[i].im[e]);
         }
     }
 }
@@ -137,10 +153,8 @@ __device__ __forceinline__ void row_product_stream(const char *ub, uint32_t row_
         for (int i = 0; i < GB; ++i) {
             if (j + i < len) {
 #pragma unroll
-                for (int e = 0; e < NB; ++e) {
-                    ar[e] += hr[i] * g[i].re[e] - hi[i] * g[i].im[e];
-                    ai[e] += hr[i] * g[i].im[e] + hi[i] * g[i].re[e];
-                }
+                for (int e = 0; e < NB; ++e)
+                    cmac<T>(ar[e], ai[e], hr[i], hi[i], g[i].re[e], g[i].im[e]);
             }
         }
     }
@@ -228,6 +242,67 @@ __device__ __forceinline__ void stage_store(const Stage<T, RPP> &st, const Block
     if (tid < RPP) s_row[tid] = st.prow;
 }
 
+// The fused step of one row given its product (ar, ai) and its own
+// operands; the moment sums of the row are added to m0..m2.
+template <typename T, int NB, int MODE, bool MOM, bool NT>
+__device__ __forceinline__ void finish_row(int64_t off, int cnt, const T (&ar)[NB],
+                                           const T (&ai)[NB], const Pack<T, NB> &uo,
+                                           const Pack<T, NB> &wo, Pack<T, NB> yv, T *wout, T *y,
+                                           T s_h, T s_u, T g0, T g1, T g2, double (&m0)[NB],
+                                           double (&m1)[NB], double (&m2)[NB])
+{
+    // explicit fused multiply-adds throughout, so that every kernel that
+    // ends in this epilogue rounds identically
+    Pack<T, NB> w;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        w.re[e] = fmadd<T>(s_h, ar[e], s_u * uo.re[e]);
+        w.im[e] = fmadd<T>(s_h, ai[e], s_u * uo.im[e]);
+    }
+    if (MODE == MODE_APPLY) {
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        if (MOM) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) {
+                const double xr = uo.re[e], xi = uo.im[e], wr = w.re[e], wi = w.im[e];
+                m0[e] += xr * xr + xi * xi;
+                m1[e] += xr * wr + xi * wi;
+                m2[e] += wr * wr + wi * wi;
+            }
+        }
+        return;
+    }
+    if (MODE == MODE_SECOND) {
+        Pack<T, NB> xn;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            w.re[e] -= wo.re[e];
+            w.im[e] -= wo.im[e];
+            xn.re[e] = fmadd<T>(g2, w.re[e], fmadd<T>(g1, uo.re[e], g0 * wo.re[e]));
+            xn.im[e] = fmadd<T>(g2, w.im[e], fmadd<T>(g1, uo.im[e], g0 * wo.im[e]));
+        }
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        store_pack_n<T, NB, NT>(y + off, xn, cnt);
+    } else {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            w.re[e] -= wo.re[e];
+            w.im[e] -= wo.im[e];
+            yv.re[e] = fmadd<T>(g0, w.re[e], yv.re[e]);
+            yv.im[e] = fmadd<T>(g0, w.im[e], yv.im[e]);
+        }
+        store_pack_n<T, NB, NT>(wout + off, w, cnt);
+        store_pack_n<T, NB, NT>(y + off, yv, cnt);
+    }
+    if (MOM) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+            m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
+            m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
+        }
+    }
+}
+
 // The fused step on one row and one pack of columns (modes as above), with
 // the moment dot products accumulated in m0..m2.
 template <typename T, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, int RPP>
@@ -252,60 +327,8 @@ __device__ __forceinline__ void step_row(int row, int64_t c0, int cnt, int len,
         row_product_staged<T, NB, GB, RPP>(ub, row_bytes, cnt, len, scol, sval, ar, ai);
     else
         row_product_stream<T, NB, GB>(ub, row_bytes, cnt, len, col, val, e0, C, ar, ai);
-    Pack<T, NB> w;
-#pragma unroll
-    for (int e = 0; e < NB; ++e) {
-        w.re[e] = s_h * ar[e] + s_u * uo.re[e];
-        w.im[e] = s_h * ai[e] + s_u * uo.im[e];
-    }
-    if (MODE == MODE_APPLY) {
-        store_pack_n<T, NB, NT>(wout + off, w, cnt);
-        if (MOM) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                const double xr = uo.re[e], xi = uo.im[e], wr = w.re[e], wi = w.im[e];
-                m0[e] += xr * xr + xi * xi;
-                m1[e] += xr * wr + xi * wi;
-                m2[e] += wr * wr + wi * wi;
-            }
-        }
-    } else if (MODE == MODE_SECOND) {
-        const Pack<T, NB> xo = wo;
-        Pack<T, NB> xn;
-#pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            w.re[e] -= xo.re[e];
-            w.im[e] -= xo.im[e];
-            xn.re[e] = g0 * xo.re[e] + g1 * uo.re[e] + g2 * w.re[e];
-            xn.im[e] = g0 * xo.im[e] + g1 * uo.im[e] + g2 * w.im[e];
-        }
-        store_pack_n<T, NB, NT>(wout + off, w, cnt);
-        store_pack_n<T, NB, NT>(y + off, xn, cnt);
-        if (MOM) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
-                m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            w.re[e] -= wo.re[e];
-            w.im[e] -= wo.im[e];
-            yv.re[e] += g0 * w.re[e];
-            yv.im[e] += g0 * w.im[e];
-        }
-        store_pack_n<T, NB, NT>(wout + off, w, cnt);
-        store_pack_n<T, NB, NT>(y + off, yv, cnt);
-        if (MOM) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) {
-                m1[e] += (double)uo.re[e] * w.re[e] + (double)uo.im[e] * w.im[e];
-                m2[e] += (double)w.re[e] * w.re[e] + (double)w.im[e] * w.im[e];
-            }
-        }
-    }
+    finish_row<T, NB, MODE, MOM, NT>(off, cnt, ar, ai, uo, wo, yv, wout, y, s_h, s_u, g0, g1, g2,
+                                     m0, m1, m2);
 }
 
 // Per-column moment partials of one row block: reduce over the rows of the
@@ -346,12 +369,12 @@ __device__ __forceinline__ void moment_partials(double (&m0)[NB], double (&m1)[N
 // One row block per workgroup; rows longer than the LDS stage read the
 // index stream directly.
 template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
-__global__ __launch_bounds__(256, 5) void k_step_sell(
+__global__ __launch_bounds__(256) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
     const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
     const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
-    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg)
+    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg, int spw, int nslab)
 {
     constexpr int RPW = 64 / LPR;        // rows per wave
     constexpr int RPP = 4 * RPW;         // rows per workgroup
@@ -376,17 +399,211 @@ __global__ __launch_bounds__(256, 5) void k_step_sell(
         lds_barrier();
     }
     const int q = wave * RPW + rsub;     // block row of this lane
-    const int64_t c0 = (int64_t)L.slab * SW + (int64_t)cl * NB;
-    const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);   // valid columns of the pack
     const int row = s_row[q];
-    double m0[NB], m1[NB], m2[NB];
+    // the workgroup's slabs (a group of spw consecutive slabs) reuse the stage
+    for (int sl = 0; sl < spw; ++sl) {
+        const int slab = (int)L.slab * spw + sl;
+        if (slab >= nslab) break;
+        const int64_t c0 = (int64_t)slab * SW + (int64_t)cl * NB;
+        const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);   // valid columns of the pack
+        double m0[NB], m1[NB], m2[NB];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
-    if (c0 < n_s && row >= 0)
-        step_row<T, NB, MODE, MOM, NT, STAGED, GB, RPP>(
-            row, c0, cnt, L.len, s_col + q, s_val + 2 * q, col, val, L.base + L.r0 + q, C, u,
-            wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
-    if (MOM) moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
+        for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
+        if (c0 < n_s && row >= 0)
+            step_row<T, NB, MODE, MOM, NT, STAGED, GB, RPP>(
+                row, c0, cnt, L.len, s_col + q, s_val + 2 * q, col, val, L.base + L.r0 + q, C,
+                u, wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
+        if (MOM)
+            moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row groups.  A lane owns the G rows of one slot group (G consecutive slots
+// of a chunk, G = 2 or 4) and one pack of columns.  Each entry of the
+// group's column union is gathered once and applied to every row of the
+// group with that row's value (zero where the row has no entry), so every
+// row still sums its own entries in column order, as in the one-row kernel.
+// For the lattice Hamiltonian the four orbital rows of a site gather 28
+// distinct rows of u: 7 gathers per row instead of 13.
+
+// The group block's index stream and value streams in LDS, in SELL order
+// (entry j of group q at j*QPW + q), padded to LS entries with (first row, 0).
+template <typename T, int G, int QPW>
+struct StageG {
+    static constexpr int PER = (QPW * LS + 255) / 256;
+    int32_t cc[PER];
+    T v[PER][2 * G];
+    int32_t prow[G];
+};
+
+template <typename T, int G>
+__device__ __forceinline__ void load_values_g(const T *val, int64_t e, T (&v)[2 * G])
+{
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const typename CVal<T>::V a =
+            *reinterpret_cast<const typename CVal<T>::V *>(val + 2 * (G * e + k));
+        v[2 * k] = a.x;
+        v[2 * k + 1] = a.y;
+    }
+}
+
+template <typename T, int G, int QPW>
+__device__ __forceinline__ void stageg_load(StageG<T, G, QPW> &st, const BlockLoc &L, int tid,
+                                            int P, int RB, const int32_t *__restrict__ perm,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val)
+{
+    static_assert(256 % QPW == 0, "a lane stages one group");
+    const int qq = tid % QPW;
+    const int64_t slot = ((int64_t)L.chunk * P + L.r0 + qq) * G;
+#pragma unroll
+    for (int k = 0; k < G; ++k) st.prow[k] = qq < RB ? perm[slot + k] : -1;
+#pragma unroll
+    for (int k = 0; k < StageG<T, G, QPW>::PER; ++k) {
+        const int t = tid + 256 * k, jj = t / QPW;
+        if (t < QPW * LS && qq < RB && jj < (int)L.len) {
+            const int64_t e = L.base + (int64_t)jj * P + L.r0 + qq;
+            st.cc[k] = col[e];
+            load_values_g<T, G>(val, e, st.v[k]);
+        }
+    }
+}
+
+template <typename T, int G, int QPW>
+__device__ __forceinline__ void stageg_store(const StageG<T, G, QPW> &st, const BlockLoc &L,
+                                             int tid, int RB, int32_t *s_col, T *s_val,
+                                             int32_t *s_row)
+{
+    const int qq = tid % QPW;
+    const int32_t self = st.prow[0] >= 0 ? st.prow[0] : 0;
+#pragma unroll
+    for (int k = 0; k < StageG<T, G, QPW>::PER; ++k) {
+        const int t = tid + 256 * k, jj = t / QPW;
+        if (t < QPW * LS && qq < RB) {
+            const bool in = jj < (int)L.len;
+            s_col[t] = in ? st.cc[k] : self;
+#pragma unroll
+            for (int r = 0; r < G; ++r)
+                store_value<T>(s_val + 2 * (G * t + r), in ? st.v[k][2 * r] : T(0),
+                               in ? st.v[k][2 * r + 1] : T(0));
+        }
+    }
+    if (tid < QPW)
+#pragma unroll
+        for (int r = 0; r < G; ++r) s_row[G * tid + r] = st.prow[r];
+}
+
+// The group's products from the LDS stage: all GB gathers of a batch are
+// issued before the first value is used.
+template <typename T, int NB, int G, int GB, int QPW>
+__device__ __forceinline__ void group_product_staged(const char *ub, uint32_t row_bytes,
+                                                     int cnt, int len, const int32_t *scol,
+                                                     const T *sval, T (&ar)[G][NB],
+                                                     T (&ai)[G][NB])
+{
+    static_assert(LS % GB == 0, "batches tile the LDS line");
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int e = 0; e < NB; ++e) ar[k][e] = ai[k][e] = T(0);
+    for (int j = 0; j < len; j += GB) {
+        int ci[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) ci[i] = scol[(j + i) * QPW];
+        Pack<T, NB> g[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+            if (j + i < len) {
+                g[i] = load_pack_n<T, NB>(row_at<T>(ub, ci[i], row_bytes), cnt);
+            } else {
+#pragma unroll
+                for (int e = 0; e < NB; ++e) g[i].re[e] = g[i].im[e] = T(0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                T hr, hi;
+                load_value<T>(sval + 2 * G * (j + i) * QPW + 2 * k, 0, hr, hi);
+#pragma unroll
+                for (int e = 0; e < NB; ++e)
+                    cmac<T>(ar[k][e], ai[k][e], hr, hi, g[i].re[e], g[i].im[e]);
+            }
+        }
+    }
+}
+
+// One block of RB <= QPW groups per workgroup (QPW = 4 * 64 / LPR groups).
+template <typename T, int LPR, int NB, int G, int MODE, bool MOM, bool NT, int GB>
+__global__ __launch_bounds__(256) void k_step_sellg(
+    const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
+    const T *__restrict__ val, int P, int RB, int lg_bpc, uint32_t nrb,
+    const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
+    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg, int spw, int nslab)
+{
+    constexpr int QPV = 64 / LPR;        // groups per wave
+    constexpr int QPW = 4 * QPV;         // groups per workgroup
+    constexpr int SW = LPR * NB;
+    __shared__ __align__(16) int32_t s_col[QPW * LS];
+    __shared__ __align__(16) T s_val[2 * G * QPW * LS];
+    __shared__ int32_t s_row[G * QPW];
+    __shared__ double red[MOM ? 4 : 1][64][3 * NB];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int qsub = lane / LPR, cl = lane % LPR;
+    const BlockLoc L = locate(xcd_remap(blockIdx.x, gridDim.x, lg_xg), nrb, lg_bpc, RB,
+                              chunk_ptr, chunk_len);
+    {
+        StageG<T, G, QPW> st;
+        stageg_load<T, G, QPW>(st, L, tid, P, RB, perm, col, val);
+        stageg_store<T, G, QPW>(st, L, tid, RB, s_col, s_val, s_row);
+        lds_barrier();
+    }
+    const int q = wave * QPV + qsub;     // group of this lane
+    int row[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) row[k] = s_row[G * q + k];
+    const uint32_t row_bytes = (uint32_t)(ld * 2 * sizeof(T));
+    // the workgroup's slabs (a group of spw consecutive slabs) reuse the stage
+    for (int sl = 0; sl < spw; ++sl) {
+        const int slab = (int)L.slab * spw + sl;
+        if (slab >= nslab) break;
+        const int64_t c0 = (int64_t)slab * SW + (int64_t)cl * NB;
+        const int cnt = (int)((n_s - c0) < NB ? (n_s - c0) : NB);
+        double m0[NB], m1[NB], m2[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
+        if (c0 < n_s && row[0] >= 0) {
+            const char *ub = reinterpret_cast<const char *>(u + 2 * c0);
+            // the rows' own operands first (a missing row reads the first one)
+            int64_t off[G];
+            Pack<T, NB> uo[G], wo[G], yv[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                off[k] = 2 * ((int64_t)(row[k] >= 0 ? row[k] : row[0]) * ld + c0);
+                uo[k] = load_pack_n<T, NB>(u + off[k], cnt);
+                if (MODE == MODE_SECOND || MODE == MODE_STEP)
+                    wo[k] = load_pack_n<T, NB, NT>(wold + off[k], cnt);
+                if (MODE == MODE_STEP) yv[k] = load_pack_n<T, NB, NT>(y + off[k], cnt);
+            }
+            T ar[G][NB], ai[G][NB];
+            group_product_staged<T, NB, G, GB, QPW>(ub, row_bytes, cnt, L.len, s_col + q,
+                                                    s_val + 2 * G * q, ar, ai);
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                if (row[k] >= 0)
+                    finish_row<T, NB, MODE, MOM, NT>(off[k], cnt, ar[k], ai[k], uo[k], wo[k],
+                                                     yv[k], wout, y, s_h, s_u, g0, g1, g2, m0,
+                                                     m1, m2);
+        }
+        if (MOM)
+            moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
+    }
 }
 
 // Moment finalisation: one workgroup per (column, quantity) sums the
@@ -434,18 +651,20 @@ constexpr int rows_per_block()
     return 4 * (64 / LPR);
 }
 
-// Row blocks of one launch: a workgroup covers min(C, 4*64/LPR) rows of one chunk.
+// Row blocks of one launch: a workgroup covers min(C, 4*64/LPR) rows of one
+// chunk, or as many row groups of a grouped chunk (C/G groups).
 int64_t sell_row_blocks(const Sell &S, int lpr)
 {
     const int rpp = 4 * (64 / lpr);
-    const int rb = S.C < rpp ? S.C : rpp;
-    return S.nchunks * (S.C / rb);
+    const int units = S.C / S.group;
+    const int rb = units < rpp ? units : rpp;
+    return S.nchunks * (units / rb);
 }
 
 // Launch geometry of the SELL kernel.
 struct SellGeom {
-    int RB, lg_bpc, lg_xg;
-    uint32_t nrb, nslab;
+    int RB, lg_bpc, lg_xg, spw;
+    uint32_t nrb, nslab, ngroups;   // row blocks, slabs, slab groups of spw
 };
 
 template <int LPR, int NB>
@@ -457,14 +676,20 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
     const int64_t nrb = sell_row_blocks(S, LPR);
     if (nrb * nslab >= ((int64_t)1 << 31) || a.ld * 16 >= ((int64_t)1 << 32))
         return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
-    g.RB = S.C < RPP ? S.C : RPP;
-    g.lg_bpc = ilog2(S.C / g.RB);
+    const int units = S.C / S.group;   // rows or row groups per chunk
+    g.RB = units < RPP ? units : RPP;
+    g.lg_bpc = ilog2(units / g.RB);
     // default placement: the row blocks of one chunk share an XCD, or, in a
     // tiled lattice order, the row blocks of one strip
-    const int64_t grp = S.group_rows > 0 ? S.group_rows / g.RB : S.C / g.RB;
+    const int64_t grp = S.group_rows > 0 ? S.group_rows / (g.RB * S.group) : units / g.RB;
     g.lg_xg = ctx->tune_xcd_group ? ilog2(ctx->tune_xcd_group) : ilog2_64(grp);
     g.nrb = (uint32_t)nrb;
     g.nslab = (uint32_t)nslab;
+    // slabs per workgroup: the stage of a row block (its index and value
+    // stream) is read from memory once per slab group; by default once per
+    // launch (all slabs)
+    g.spw = (int)std::min<int64_t>(nslab, ctx->tune_slabs > 0 ? ctx->tune_slabs : nslab);
+    g.ngroups = (uint32_t)((nslab + g.spw - 1) / g.spw);
     return CHEBFD_OK;
 }
 
@@ -473,10 +698,11 @@ void launch_sell_k(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const Sell
 {
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
     hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB>),
-                       dim3(g.nrb * g.nslab), dim3(256), 0, ctx->stream, S.chunk_ptr,
+                       dim3(g.nrb * g.ngroups), dim3(256), 0, ctx->stream, S.chunk_ptr,
                        S.chunk_len, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
                        (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
-                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.lg_xg);
+                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.lg_xg, g.spw,
+                       (int)g.nslab);
 }
 
 template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT>
@@ -484,6 +710,18 @@ int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
 {
     SellGeom g;
     if (int rc = sell_geom<LPR, NB>(ctx, S, a, g)) return rc;
+    if (S.group > 1) {
+        const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
+        const auto kern = S.group == 4 ? k_step_sellg<T, LPR, NB, 4, MODE, MOM, NT, 16>
+                                       : k_step_sellg<T, LPR, NB, 2, MODE, MOM, NT, 16>;
+        hipLaunchKernelGGL(kern, dim3(g.nrb * g.ngroups), dim3(256), 0, ctx->stream,
+                           S.chunk_ptr, S.chunk_len, S.perm, S.col, val, S.C / S.group, g.RB,
+                           g.lg_bpc, g.nrb, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
+                           (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
+                           a.partials, g.lg_xg, g.spw, (int)g.nslab);
+        CHEBFD_CHECK_LAUNCH();
+        return CHEBFD_OK;
+    }
     // rows that fit the LDS stage -> staged variant, else the index stream
     if (S.max_len <= LS)
         launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16>(ctx, S, a, g);

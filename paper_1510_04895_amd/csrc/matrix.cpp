@@ -2,6 +2,8 @@
 // (Eq. (Ham)), CSR -> SELL-C-sigma conversion (Sec. 4.2), Gershgorin bounds
 // (Sec. 3.1 step 1) and upload to the device.
 #include <algorithm>
+#include <climits>
+#include <iterator>
 #include <cmath>
 #include <complex>
 #include <numeric>
@@ -101,9 +103,13 @@ void free_matrix(chebfd_matrix *H)
 // Builds SELL-C-sigma from a row generator.  rowfn(i, entries) fills row i.
 // `order` (optional) is the sequence in which rows are cut into sigma windows
 // and chunks (the traversal order of the fused step); nullptr = 0, 1, ...
+// `grouped` asks for the row-group layout (see Sell): -1 where it pays (4,
+// then 2 rows per group), 2 or 4 that group size whenever every union fits
+// the LDS stage, 0 or 1 never; groups are consecutive slots (after the
+// `pair_rows` placement, which puts rows with equal columns side by side).
 template <typename RowFn>
 int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool pair_rows,
-               const std::vector<int32_t> *order = nullptr)
+               const std::vector<int32_t> *order = nullptr, int grouped = 0)
 {
     Sell &S = H->sell;
     S.n = n;
@@ -187,6 +193,110 @@ int build_sell(chebfd_matrix *H, int64_t n, int C, int sigma, RowFn rowfn, bool 
             std::copy(order.begin(), order.end(), perm.begin() + c * C);
         }
     }
+    if (grouped != 0 && grouped != 1) {
+        // union columns of groups of G consecutive slots (each row's entries
+        // are sorted by column); a group size is taken when every union fits
+        // the kernel's LDS stage and (automatic choice) the unions save at
+        // least a quarter of the gathers; the automatic choice tries 4, then 2
+        std::vector<Entry> er;
+        std::vector<int64_t> cur, nxt, rc;
+        auto unions = [&](int G, std::vector<int32_t> &ulen, int64_t &sum_u, int64_t &sum_r,
+                          int &max_u) {
+            const int P = C / G;
+            ulen.assign((size_t)S.nchunks * P, 0);
+            sum_u = sum_r = 0;
+            max_u = 0;
+            for (int64_t c = 0; c < S.nchunks; ++c)
+                for (int q = 0; q < P; ++q) {
+                    cur.clear();
+                    for (int k = 0; k < G; ++k) {
+                        const int32_t i = perm[c * C + G * q + k];
+                        if (i < 0) continue;
+                        rowfn(i, er);
+                        sum_r += (int64_t)er.size();
+                        rc.clear();
+                        for (const Entry &e : er) rc.push_back(e.c);
+                        nxt.clear();
+                        std::set_union(cur.begin(), cur.end(), rc.begin(), rc.end(),
+                                       std::back_inserter(nxt));
+                        cur.swap(nxt);
+                    }
+                    ulen[c * P + q] = (int32_t)cur.size();
+                    sum_u += (int64_t)cur.size();
+                    max_u = std::max(max_u, (int)cur.size());
+                }
+        };
+        std::vector<int32_t> ulen;
+        int64_t sum_u = 0, sum_r = 0;
+        int max_u = 0, G = 0;
+        for (int g : {4, 2}) {
+            if (grouped > 0 && g != grouped) continue;
+            if (C % g) continue;
+            unions(g, ulen, sum_u, sum_r, max_u);
+            if (max_u <= kStageLen && (grouped > 0 || 4 * sum_u <= 3 * sum_r)) {
+                G = g;
+                break;
+            }
+        }
+        if (G > 0) {
+            S.group = G;
+            const int P = C / G;
+            std::vector<int64_t> cptr(S.nchunks + 1, 0);
+            std::vector<int32_t> clen(S.nchunks, 0);
+            for (int64_t c = 0; c < S.nchunks; ++c) {
+                int w = 0;
+                for (int q = 0; q < P; ++q) w = std::max(w, ulen[c * P + q]);
+                clen[c] = w;
+                cptr[c + 1] = cptr[c] + (int64_t)w * P;
+            }
+            S.max_len = max_u;
+            S.stored = cptr[S.nchunks];
+            std::vector<int32_t> col(S.stored);
+            std::vector<double> v64(2 * G * S.stored, 0.0);
+            std::vector<float> v32(2 * G * S.stored, 0.0f);
+            std::vector<std::vector<Entry>> rows(G);
+            std::vector<size_t> at(G);
+            for (int64_t c = 0; c < S.nchunks; ++c)
+                for (int q = 0; q < P; ++q) {
+                    int32_t self = -1;
+                    for (int k = 0; k < G; ++k) {
+                        const int32_t i = perm[c * C + G * q + k];
+                        if (i >= 0) rowfn(i, rows[k]);
+                        else rows[k].clear();
+                        if (self < 0 && i >= 0) self = i;
+                        at[k] = 0;
+                    }
+                    // padding: the group's first row (or row 0) with zero values
+                    if (self < 0) self = 0;
+                    for (int j = 0; j < clen[c]; ++j) {
+                        const int64_t e = cptr[c] + (int64_t)j * P + q;
+                        // next union column: the smallest pending one
+                        int64_t cc = INT64_MAX;
+                        for (int k = 0; k < G; ++k)
+                            if (at[k] < rows[k].size()) cc = std::min(cc, rows[k][at[k]].c);
+                        if (cc == INT64_MAX) {
+                            col[e] = self;
+                            continue;
+                        }
+                        col[e] = (int32_t)cc;
+                        for (int k = 0; k < G; ++k)
+                            if (at[k] < rows[k].size() && rows[k][at[k]].c == cc) {
+                                const cd v = rows[k][at[k]++].v;
+                                v64[2 * (G * e + k)] = v.real();
+                                v64[2 * (G * e + k) + 1] = v.imag();
+                                v32[2 * (G * e + k)] = (float)v.real();
+                                v32[2 * (G * e + k) + 1] = (float)v.imag();
+                            }
+                    }
+                }
+            int rc2;
+            if ((rc2 = upload(&S.chunk_ptr, cptr)) || (rc2 = upload(&S.chunk_len, clen)) ||
+                (rc2 = upload(&S.perm, perm)) || (rc2 = upload(&S.col, col)) ||
+                (rc2 = upload(&S.val64, v64)) || (rc2 = upload(&S.val32, v32)))
+                return rc2;
+            return CHEBFD_OK;
+        }
+    }
     std::vector<int64_t> cptr(S.nchunks + 1, 0);
     std::vector<int32_t> clen(S.nchunks, 0);
     int max_len = 0;
@@ -255,10 +365,11 @@ std::vector<int32_t> ti_tiled_rows(const int L[3], int w)
 
 }  // namespace
 
-// Default strip width of the tiled lattice order (sites along x).
-int default_tile(const chebfd_ctx *ctx)
+// Default strip width of the tiled lattice order (sites along x): 2 for the
+// SELL row order, 4 for the matrix-free step (measured at 256x256x64).
+int default_tile(const chebfd_ctx *ctx, bool sell)
 {
-    return ctx->tune_tile >= 0 ? ctx->tune_tile : 4;
+    return ctx->tune_tile >= 0 ? ctx->tune_tile : (sell ? 2 : 4);
 }
 
 // Whether the tiled lattice order pays: in column-slab-major order a site's
@@ -306,7 +417,8 @@ extern "C" int chebfd_matrix_from_csr(chebfd_ctx *ctx, int64_t n, const int64_t 
         for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
             r.push_back({(int64_t)col[p], cd(val[2 * p], val[2 * p + 1])});
     };
-    int rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
+    int rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0, nullptr,
+                        ctx->tune_row_group);
     if (rc) {
         free_matrix(H);
         delete H;
@@ -350,13 +462,15 @@ extern "C" int chebfd_matrix_ti(chebfd_ctx *ctx, int Lx, int Ly, int Lz, int pbc
     if (storage == CHEBFD_STORAGE_SELL) {
         // the fused step's slab row: 32 lanes of 16 bytes
         const int w = ctx->tune_tile >= 0 || tiled_order_pays(L, 512)
-                          ? std::min(default_tile(ctx), Lx) : 0;
+                          ? std::min(default_tile(ctx, true), Lx) : 0;
         if (w > 0) {
             const std::vector<int32_t> order = ti_tiled_rows(L, w);
-            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0, &order);
+            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0, &order,
+                            ctx->tune_row_group);
             H->sell.group_rows = (int64_t)4 * w * Ly * Lz;
         } else {
-            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0);
+            rc = build_sell(H, n, sell_C, sell_sigma, rowfn, ctx->tune_pair_rows != 0, nullptr,
+                            ctx->tune_row_group);
         }
     } else {
         Stencil &S = H->st;
@@ -419,9 +533,11 @@ extern "C" int chebfd_matrix_info(const chebfd_matrix *H, int64_t *n, int64_t *n
     if (g_hi) *g_hi = H->g_hi;
     // one step reads every stored entry once: value + column index, plus the
     // chunk pointers/lengths and the slot permutation
+    // (a row-group layout stores one index and G values per entry)
+    const int64_t nv = sell && H->sell.group > 1 ? H->sell.group : 1;
     if (matrix_bytes_c128)
-        *matrix_bytes_c128 = sell ? H->sell.stored * (16 + 4) : (H->n / 4) * 8;
-    if (matrix_bytes_c64) *matrix_bytes_c64 = sell ? H->sell.stored * (8 + 4) : (H->n / 4) * 4;
+        *matrix_bytes_c128 = sell ? H->sell.stored * (nv * 16 + 4) : (H->n / 4) * 8;
+    if (matrix_bytes_c64) *matrix_bytes_c64 = sell ? H->sell.stored * (nv * 8 + 4) : (H->n / 4) * 4;
     return CHEBFD_OK;
 }
 

@@ -39,6 +39,9 @@
 
 struct chebfd_result {
     std::vector<double> evals, res, evecs;
+    // precision form: the in-window Ritz pairs of the complex64 sweep whose
+    // residual was below sqrt(eps), at its last iteration (before the polish)
+    std::vector<double> sweep_evals, sweep_res;
     chebfd_stats stats{};
 };
 
@@ -407,6 +410,21 @@ struct Solver {
                 // then sits at the FP32 rounding floor, where its residual is
                 // rounding noise that one FP64 pass filters out, and the few
                 // pairs above it converge in the same polish passes
+                {
+                    // record the sweep's result (ascending); the last
+                    // iteration of the FP32 phase leaves it in the result
+                    std::vector<std::pair<double, double>> sp;
+                    for (int j = 0; j < k; ++j)
+                        if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi && res[j] <= seps)
+                            sp.push_back({theta[j], res[j]});
+                    std::sort(sp.begin(), sp.end());
+                    out->sweep_evals.clear();
+                    out->sweep_res.clear();
+                    for (const auto &q : sp) {
+                        out->sweep_evals.push_back(q.first);
+                        out->sweep_res.push_back(q.second);
+                    }
+                }
                 const double sw = std::max(std::fabs(a), std::fabs(b));
                 const double thr = std::isnan(p.polish_switch) ? 8.0 * 0x1p-23 * sw : p.polish_switch;
                 const bool below = ngood > 0 && (mx <= thr || med <= 0.5 * thr);
@@ -731,6 +749,16 @@ extern "C" int chebfd_result_get(const chebfd_result *r, int64_t *n_found, const
     if (residuals) *residuals = r->res.data();
     if (evecs) *evecs = r->evecs.empty() ? nullptr : r->evecs.data();
     if (stats) *stats = r->stats;
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_result_sweep(const chebfd_result *r, int64_t *n, const double **evals,
+                                   const double **residuals)
+{
+    if (!r) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_result_sweep: NULL result");
+    if (n) *n = (int64_t)r->sweep_evals.size();
+    if (evals) *evals = r->sweep_evals.data();
+    if (residuals) *residuals = r->sweep_res.data();
     return CHEBFD_OK;
 }
 

@@ -132,24 +132,41 @@ def test_filter_c64_vs_reference(env, orc, storage):
     assert relerr(got, ref) < tol
 
 
-@pytest.mark.parametrize("kind,tile", [("ti", 0), ("ti", 4), ("ti", 5), ("csr", -1)])
+@pytest.mark.parametrize("kind,tile,group", [("ti", 0, -1), ("ti", 4, -1), ("ti", 5, -1),
+                                             ("ti", 0, 1), ("ti", 4, 2), ("csr", -1, -1),
+                                             ("csr", -1, 2), ("ti_csr", -1, 4)])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_filter_many_blocks_per_workgroup(env, orc, kind, tile, prec):
+def test_filter_many_blocks_per_workgroup(env, orc, kind, tile, group, prec):
     """Tens of thousands of row blocks, a ragged last chunk and moments on;
     the TI matrix in lattice row order and in the tiled row order (strips of
-    4 or 5 x-columns, the latter leaving a ragged last strip), the random
-    matrix in its own order."""
+    4 or 5 x-columns, the latter leaving a ragged last strip), in the
+    row-group layout (default: the 4 orbital rows of a site), in pairs and
+    one row per slot; the random matrix (odd N) one row per slot (default:
+    its rows share few columns) and forced into pairs (short rows, so that
+    every union fits the stage); the lattice matrix handed over as plain
+    CSR (23^3 sites, a ragged last chunk) forced into groups of 4.  The
+    matrix bytes per stored entry show which layout was built."""
     torch, B, ctx = env
     B.chebfd_set_tuning(ctx, "tile", tile)
+    B.chebfd_set_tuning(ctx, "row_group", group)
     if kind == "ti":
         L = (24, 24, 23)
         Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=6)
         H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=6, storage=B.STORAGE_SELL)
+    elif kind == "ti_csr":
+        Hr = orc.ti_hamiltonian(23, 23, 23, pbc=3, V=1.0, seed=6)
+        H = B.Matrix.from_csr(ctx, Hr.rowptr, Hr.col, Hr.val, sell_C=32, sell_sigma=256)
     else:
         n = 50021
-        rp, col, val = inp.random_hermitian_csr(n, seed=9, min_row=2, max_row=28)
+        rp, col, val = inp.random_hermitian_csr(n, seed=9, min_row=2,
+                                                max_row=28 if group < 2 else 4)
         Hr = orc.CSR(n, rp, col, val)
         H = B.Matrix.from_csr(ctx, rp, col, val, sell_C=32, sell_sigma=256)
+    info = H.info()
+    # a row-group layout stores one index and G complex128 values per entry
+    per_entry = info["matrix_bytes_c128"] // info["padded"]
+    G = 4 if (kind.startswith("ti") and group == -1) else (1 if group < 2 else group)
+    assert per_entry == 4 + 16 * G, (per_entry, G)
     a, b = orc.gershgorin(Hr)
     n_s, n_p = 64, 5
     X = inp.random_block(Hr.n, n_s, seed=12)
@@ -166,6 +183,7 @@ def test_filter_many_blocks_per_workgroup(env, orc, kind, tile, prec):
         torch.cuda.synchronize()
     finally:
         B.chebfd_set_tuning(ctx, "tile", -1)
+        B.chebfd_set_tuning(ctx, "row_group", -1)
     got = Xd.cpu().numpy().astype(np.complex128)
     m = mom.cpu().numpy()
     if prec == "c128":
@@ -189,16 +207,23 @@ def test_launch_settings_give_identical_blocks(env, storage):
     gam = inp.random_gamma(n_p, seed=6)
     if storage == "sell":
         # (build-time tile, launch settings): lattice and tiled row orders
+        # default: the 4 orbital rows of a site per group; row_group=1: one
+        # row per slot
         settings = [(0, dict()), (0, dict(lanes=64)), (0, dict(lanes=16)),
                     (0, dict(xcd_group=1)), (0, dict(xcd_group=8)), (4, dict()),
                     (2, dict(lanes=64)), (5, dict(xcd_group=1)), (4, dict(nontemporal=0)),
-                    (0, dict(pair_rows=0))]
+                    (0, dict(row_group=1)), (0, dict(row_group=1, lanes=64)),
+                    (4, dict(row_group=1, lanes=16)), (0, dict(row_group=1, pair_rows=0)),
+                    (0, dict(row_group=2)), (4, dict(row_group=2, lanes=16)),
+                    (0, dict(pair_rows=0, row_group=2)), (0, dict(slabs=1)),
+                    (0, dict(slabs=2, lanes=16)), (2, dict(slabs=1, row_group=1))]
     else:
         settings = [(-1, dict()), (-1, dict(lanes=64)), (-1, dict(lanes=16)),
                     (-1, dict(xcd_group=1)), (-1, dict(order=0)), (-1, dict(order=1)),
                     (2, dict(order=1, lanes=64)), (16, dict(order=1, xcd_group=1)),
                     (4, dict(order=1, lanes=16)), (-1, dict(order=1, nontemporal=0))]
-    defaults = dict(lanes=0, order=-1, xcd_group=0, nontemporal=1, pair_rows=1)
+    defaults = dict(lanes=0, order=-1, xcd_group=0, nontemporal=1, pair_rows=1, row_group=-1,
+                    slabs=0)
     outs, moms = [], []
     try:
         for tile, cfg in settings:
@@ -500,3 +525,92 @@ def test_solve_with_lanczos_bounds(env, orc, steps):
     assert info["g_lo"] <= stats["a"] < gold.min() and gold.max() < stats["b"] <= info["g_hi"]
     if steps == 40:
         assert stats["b"] - stats["a"] < 0.8 * (info["g_hi"] - info["g_lo"])
+
+
+def test_solve_c64_narrow_interval_overflow_restarts(env, orc):
+    """Two Lanczos steps give an interval far inside the spectrum; a degree
+    of 2000 then grows T_n(x) beyond the FP32 range outside it (the
+    complex64 sweep overflows before any Rayleigh quotient is seen).  The
+    solver must take the overflow as proof of a too-narrow interval, restart
+    on the Gershgorin interval, and return the dense oracle's eigenvalues."""
+    torch, B, ctx = env
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                   "ti_8x8x8_V1_seed1_evals.txt"))
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=1)
+    # a start-vector seed whose two-step estimate (the solver's own call:
+    # same seed, same padding) misses part of the spectrum
+    seed = next(s for s in range(1, 41)
+                if (lambda ab: ab[1] < gold.max() or ab[0] > gold.min())(
+                    B.chebfd_lanczos_bounds(ctx, H, k=2, seed=s)))
+    aw = np.sort(np.abs(gold))
+    d = 0.5 * (aw[15] + aw[16])
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=2000, eps=1e-9, seed=seed, bounds=2,
+                         precision=B.PREC_C64)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    info = H.info()
+    want = np.sort(gold[np.abs(gold) <= d])
+    S_w = max(abs(info["g_lo"]), abs(info["g_hi"]))
+    assert rc == 0 and ev.size == want.size == 16, (rc, ev, stats)
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    assert stats["a"] == info["g_lo"] and stats["b"] == info["g_hi"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_precision_sweep_vs_golden(env, orc, seed):
+    """The precision form on the correctness configuration (8x8x8, 16
+    eigenvalues, N_S 32, N_p 200): before the FP64 polish, the complex64
+    sweep's in-window Ritz values with residual below sqrt(eps) are all 16
+    dense-oracle eigenvalues to 1e-5 S_w; after the polish all 16 agree to
+    1e-10 S_w with residual <= 1e-9."""
+    torch, B, ctx = env
+    w = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                f"ti_8x8x8_V1_seed{seed}_evals.txt"))
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[15] + aw[16])
+    want = np.sort(w[np.abs(w) <= d])
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=seed)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=200, eps=1e-9, seed=seed + 1000,
+                         max_iter=200, precision=B.PREC_C64)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0, stats
+    sw = stats["sweep_evals"]
+    assert stats["iterations_c64"] >= 1
+    assert sw.size == 16, sw
+    err32 = np.abs(sw - want).max() / S_w
+    assert err32 < 1e-5, err32
+    assert stats["sweep_residuals"].max() <= math.sqrt(1e-9)
+    assert ev.size == 16 and np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    print(f"seed {seed}: sweep eigenvalue error {err32:.2e} S_w, sweep residuals "
+          f"{stats['sweep_residuals'].min():.1e}..{stats['sweep_residuals'].max():.1e}")
+
+
+def test_svqb_refills_a_rank_deficient_block(env, orc):
+    """A diagonal matrix with 4 eigenvalues in the window and the other 60
+    at the ends of the spectrum: after one filter pass of degree 400 the 16
+    search vectors span numerically only the 4 wanted directions (the rest
+    is damped by ~1e-30), so SVQB must drop directions and refill them with
+    random vectors orthogonalised against the kept ones (Sec. 3.1 step 6).
+    The solve still returns exactly the 4 eigenvalues with orthonormal
+    vectors."""
+    torch, B, ctx = env
+    lam = np.concatenate([np.linspace(-1.0, -0.9, 30), [-0.03, -0.01, 0.02, 0.04],
+                          np.linspace(0.9, 1.0, 30)])
+    n = lam.size
+    rp = np.arange(n + 1, dtype=np.int64)
+    col = np.arange(n, dtype=np.int32)
+    val = lam.astype(np.complex128)
+    H = B.Matrix.from_csr(ctx, rp, col, val, sell_C=32, sell_sigma=32)
+    p = B.default_params(lam_lo=-0.05, lam_hi=0.05, n_s=16, n_p=400, eps=1e-9, seed=4,
+                         max_iter=20)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    assert stats["refilled"] > 0, stats
+    assert rc == 0 and ev.size == 4, (rc, ev, stats)
+    assert np.abs(ev - np.array([-0.03, -0.01, 0.02, 0.04])).max() < 1e-12
+    assert rs.max() <= 1e-9
+    assert np.abs(V.conj().T @ V - np.eye(4)).max() < 1e-10
+    Hr = orc.CSR(n, rp, col, val)
+    r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
+    assert r.max() <= 1.05e-9

@@ -64,10 +64,15 @@ def test_noalloc_matches_filter_apply(env, storage, dtype_name):
 
 
 def test_noalloc_rejects_oversized_partials(env):
-    """32x32x32 SELL-32 with 256 columns needs 16384 row blocks x 256 x 24 B
-    = 100.7 MB of partial sums, more than the 64 MiB array."""
+    """32x32x32 SELL-32 (one row per slot) with 256 columns needs 16384 row
+    blocks x 256 x 24 B = 100.7 MB of partial sums, more than the 64 MiB
+    array."""
     torch, B, ctx = env
-    H = B.Matrix.ti(ctx, (32, 32, 32), pbc=3, V=1.0, seed=1)
+    B.chebfd_set_tuning(ctx, "row_group", 1)
+    try:
+        H = B.Matrix.ti(ctx, (32, 32, 32), pbc=3, V=1.0, seed=1)
+    finally:
+        B.chebfd_set_tuning(ctx, "row_group", -1)
     n = H.info()["n"]
     X = torch.zeros((n, 256), dtype=torch.complex128, device="cuda")
     U, W = torch.empty_like(X), torch.empty_like(X)
