@@ -6,10 +6,12 @@ all window eigenpairs (residual < 1e-9).
                     [--kernel-only] [--no-cpu-baseline]
 
 Headline (the largest single-GPU lattice, 256x256x64, N = 16,777,216, 128
-search vectors in complex128, SELL-32-256): a step is one fused launch of
-the Chebyshev filter (Fig. fig:ChebFD: the sparse matrix-multiple-vector
-product fused with the three-term recurrence and the filter accumulation,
-Sec. 4), with the matrix and the three blocks resident in HBM.  The timed
+search vectors in complex128, the lattice Hamiltonian applied matrix-free;
+`kernels` gives the same step on the stored SELL-32-256 matrix and both in
+complex64): a step is one fused launch of the Chebyshev filter (Fig.
+fig:ChebFD: the sparse matrix-multiple-vector product fused with the
+three-term recurrence and the filter accumulation, Sec. 4), with the matrix
+(or the site potentials) and the three blocks resident in HBM.  The timed
 region is one filter application of degree K, i.e. exactly K fused launches
 (the first two set up the recurrence); `value` is their algorithmic bytes
 (the matrix once, u read once, w and x read and written, per launch)
@@ -213,7 +215,7 @@ def main():
                     help="fused launches in the timed region (one filter of this degree)")
     ap.add_argument("--warmup", type=int, default=5, help="untimed fused launches first")
     ap.add_argument("--workload", default="ti_256x256x64")
-    ap.add_argument("--storage", default="sell", choices=["sell", "stencil"])
+    ap.add_argument("--storage", default="stencil", choices=["sell", "stencil"])
     ap.add_argument("--precision", default="c128", choices=["c128", "c64"])
     ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1],
                     help="block order of the matrix-free step (tuning key 'order'): -1 "

@@ -38,7 +38,12 @@ def _pmc(path):
 
 
 def _mode(name):
-    m = re.search(r"k_step_(sell|ti)\w*<[^,]+, \d+, \d+, (\d)", name)
+    """MODE template argument of a fused-step kernel name (k_step_sellg
+    carries the row-group size before it)."""
+    m = re.search(r"k_step_sellg<[^,]+, \d+, \d+, \d+, (\d)", name)
+    if m:
+        return int(m.group(1))
+    m = re.search(r"k_step_(sell|ti)<[^,]+, \d+, \d+, (\d)", name)
     return int(m.group(2)) if m else None
 
 
