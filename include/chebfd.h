@@ -500,6 +500,25 @@ int chebfd_result_get(const chebfd_result *r, int64_t *n_found, const double **e
                       const double **residuals, const double **evecs, chebfd_stats *stats);
 int chebfd_result_destroy(chebfd_result *r);
 
+/* Convergence history, one entry per outer iteration (Sec. 3.1 step 8):
+ * the matrix-vector products so far (sum of active columns times n_p), the
+ * phase's precision, the pairs locked before the iteration, the in-window
+ * Ritz pairs with residual <= eps (converged) and <= sqrt(eps) (accepted,
+ * i.e. not ghosts), the smallest residual of an in-window Ritz pair and the
+ * largest residual of an accepted or locked one (NaN if none).  After a
+ * restart on the Gershgorin interval the history is the restarted run's. */
+typedef struct {
+    int64_t n_mvm;
+    int precision;
+    int n_locked;
+    int n_converged;
+    int n_accepted;
+    double r_min;
+    double r_max_accepted;
+} chebfd_iter_info;
+
+int chebfd_result_history(const chebfd_result *r, int64_t *n, const chebfd_iter_info **history);
+
 /* Precision form (CHEBFD_PREC_C64): the result of the complex64 sweep
  * before the FP64 polish -- the in-window Ritz values of its last iteration
  * (Rayleigh-Ritz in FP64 on the FP32-filtered block) whose residual

@@ -47,6 +47,15 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class IterInfo(C.Structure):
+    _fields_ = [("n_mvm", C.c_int64), ("precision", C.c_int), ("n_locked", C.c_int),
+                ("n_converged", C.c_int), ("n_accepted", C.c_int), ("r_min", C.c_double),
+                ("r_max_accepted", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -89,6 +98,7 @@ def lib():
         "chebfd_host_eigh": (i32, [i32, vp, vp]),
         "chebfd_set_tuning": (i32, [vp, C.c_char_p, i32]),
         "chebfd_result_sweep": (i32, [vp, vp, vp, vp]),
+        "chebfd_result_history": (i32, [vp, vp, vp]),
         "chebfd_bandwidth_probe": (i32, [vp, vp, i64, i32, vp]),
         "chebfd_dos_params": (i32, [vp, i32, i64, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, vp,
                                     vp, vp, vp]),
@@ -133,7 +143,8 @@ def exported_symbols():
                         "chebfd_gram chebfd_block_times chebfd_residual_norms "
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
                         "chebfd_params_default chebfd_solve_workspace_size chebfd_solve "
-                        "chebfd_result_get chebfd_result_sweep chebfd_result_destroy chebfd_set_tuning "
+                        "chebfd_result_get chebfd_result_sweep chebfd_result_history chebfd_result_destroy "
+                        "chebfd_set_tuning "
                         "chebfd_bandwidth_probe chebfd_dos_params chebfd_learned_features "
                         "chebfd_learned_decode chebfd_fit_corrections chebfd_mlp_create "
                         "chebfd_mlp_destroy chebfd_mlp_num_params chebfd_mlp_get_params "
@@ -545,6 +556,10 @@ def chebfd_solve(ctx, H, params: Params):
         m = ns_.value
         stats["sweep_evals"] = np.ctypeslib.as_array(ev, (m,)).copy() if m else np.empty(0)
         stats["sweep_residuals"] = np.ctypeslib.as_array(rs, (m,)).copy() if m else np.empty(0)
+        # convergence history (one record per outer iteration)
+        hp = C.POINTER(IterInfo)()
+        _check(lib().chebfd_result_history(res, C.byref(ns_), C.byref(hp)))
+        stats["history"] = [hp[i].as_dict() for i in range(ns_.value)]
         return rc, evals, resid, vecs, stats
     finally:
         lib().chebfd_result_destroy(res)

@@ -89,24 +89,25 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
     int64_t slab, sb, site;
     bool in_lattice;
     if (order == 1) {
-        // tiled lattice order: a block is SPB z-consecutive sites of one
-        // (x, y) column; z-blocks run fastest, then the `tile` x-columns of
-        // a strip, then y, then strips, then slabs (tile divides Lx), so
-        // every neighbour of a site is gathered at most one strip-row of
-        // work apart, on the XCD that runs the strip
-        const int64_t nzb = (Lz + SPB - 1) / SPB;
-        const int64_t per_strip = (int64_t)tile * Ly * nzb;
+        // tiled lattice order: inside a strip row (the `tile` x-columns of
+        // one y), sites run z fastest, then x; a block is SPB consecutive
+        // sites of a strip row (the last one ragged); then y, then strips,
+        // then slabs (tile divides Lx), so every neighbour of a site is
+        // gathered at most one strip row of work apart, on the XCD that runs
+        // the strip
+        const int64_t row_sites = (int64_t)tile * Lz;
+        const int64_t bpr = (row_sites + SPB - 1) / SPB;   // blocks per strip row
+        const int64_t per_strip = bpr * Ly;
         const int64_t nper = (Lx / tile) * per_strip;
         slab = b / nper;
         sb = b - slab * nper;
         const int64_t strip = sb / per_strip;
         const int64_t r = sb - strip * per_strip;
-        const int64_t t = r / nzb;
-        const int zb = (int)(r - t * nzb);
-        const int64_t yy0 = t / tile;
-        const int xl = (int)(t - yy0 * tile);
-        const int z = zb * SPB + wave * SPW + ssub;
-        in_lattice = z < Lz;
+        const int64_t yy0 = r / bpr;
+        const int64_t sr = (r - yy0 * bpr) * SPB + wave * SPW + ssub;   // site in strip row
+        in_lattice = sr < row_sites;
+        const int64_t xl = sr / Lz;
+        const int z = (int)(sr - xl * Lz);
         site = (strip * tile + xl) + (int64_t)Lx * (yy0 + (int64_t)Ly * z);
     } else {
         // column-slab major, sites in lattice order
@@ -305,16 +306,17 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     int tile = std::min(default_tile(ctx, false), S.L[0]);
     while (tile > 1 && S.L[0] % tile) --tile;
     if (order == 1 && tile < 1) order = 0;
-    const int64_t nzb = (S.L[2] + SPB - 1) / SPB;
-    // tiled blocks cover z-runs of SPB sites (the last one of a column ragged)
-    const int64_t nblk = order == 1 ? (int64_t)S.L[0] * S.L[1] * nzb : (nsites + SPB - 1) / SPB;
+    // tiled blocks: SPB consecutive sites of a strip row (the last ragged)
+    const int64_t bpr = ((int64_t)tile * S.L[2] + SPB - 1) / SPB;
+    const int64_t nblk = order == 1 ? (int64_t)(S.L[0] / tile) * S.L[1] * bpr
+                                    : (nsites + SPB - 1) / SPB;
     const int64_t nslab = (a.n_s + SW - 1) / SW;
     if (nblk * nslab >= ((int64_t)1 << 31))
         return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
     if (n_part) *n_part = nblk;
     // default placement in the tiled order: one strip of blocks per XCD group
     int lg_xg = ilog2(ctx->tune_xcd_group);
-    if (order == 1 && !ctx->tune_xcd_group) lg_xg = ilog2_64((int64_t)tile * S.L[1] * nzb);
+    if (order == 1 && !ctx->tune_xcd_group) lg_xg = ilog2_64(bpr * S.L[1]);
     const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
     hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
                        dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,

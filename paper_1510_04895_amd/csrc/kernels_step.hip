@@ -798,7 +798,8 @@ int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int p
     const int nb = precision == CHEBFD_PREC_C128 ? 1 : 2;
     const int lpr = pick_lpr(ctx, n_s, nb);
     if (H->storage == CHEBFD_STORAGE_SELL) return sell_row_blocks(H->sell, lpr);
-    // the larger of the two stencil block counts (site-linear and tiled)
+    // the larger of the two stencil block counts (site-linear and tiled;
+    // strips of one column give the most tiled blocks)
     const Stencil &T = H->st;
     const int64_t spb = 4 * (64 / lpr);
     const int64_t lin = (H->n / 4 + spb - 1) / spb;

@@ -42,6 +42,7 @@ struct chebfd_result {
     // precision form: the in-window Ritz pairs of the complex64 sweep whose
     // residual was below sqrt(eps), at its last iteration (before the polish)
     std::vector<double> sweep_evals, sweep_res;
+    std::vector<chebfd_iter_info> history;   // one entry per outer iteration
     chebfd_stats stats{};
 };
 
@@ -379,6 +380,30 @@ struct Solver {
                 if (res[j] <= seps) ++nconving;
                 rmin = std::min(rmin, res[j]);
                 if (res[j] <= seps) worst = std::max(worst, res[j]);
+            }
+            {
+                // convergence history: residuals of the in-window Ritz pairs
+                // of this iteration (and of the pairs locked before it)
+                chebfd_iter_info h{};
+                h.n_mvm = st.n_mvm;
+                h.precision = prec;
+                h.n_locked = n_lock;
+                h.n_converged = nconv;
+                h.n_accepted = nconv + nconving;
+                h.r_min = INFINITY;
+                h.r_max_accepted = 0.0;
+                for (int j = 0; j < k; ++j)
+                    if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi) {
+                        h.r_min = std::min(h.r_min, res[j]);
+                        if (res[j] <= seps) h.r_max_accepted = std::max(h.r_max_accepted, res[j]);
+                    }
+                for (double r : lock_res) {
+                    h.r_min = std::min(h.r_min, r);
+                    h.r_max_accepted = std::max(h.r_max_accepted, r);
+                }
+                if (h.n_accepted + n_lock == 0) h.r_max_accepted = NAN;
+                if (!std::isfinite(h.r_min)) h.r_min = NAN;
+                out->history.push_back(h);
             }
             if (p.verbose) {
                 std::fprintf(stderr,
@@ -759,6 +784,15 @@ extern "C" int chebfd_result_sweep(const chebfd_result *r, int64_t *n, const dou
     if (n) *n = (int64_t)r->sweep_evals.size();
     if (evals) *evals = r->sweep_evals.data();
     if (residuals) *residuals = r->sweep_res.data();
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_result_history(const chebfd_result *r, int64_t *n,
+                                     const chebfd_iter_info **history)
+{
+    if (!r) return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_result_history: NULL result");
+    if (n) *n = (int64_t)r->history.size();
+    if (history) *history = r->history.data();
     return CHEBFD_OK;
 }
 

@@ -418,6 +418,14 @@ def test_solve_small_lattice_vs_dense(env, orc, storage, prec, lock):
     r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
     assert r.max() <= 1.05e-9
     assert np.abs(V.conj().T @ V - np.eye(4)).max() < 1e-9
+    # convergence history: one record per iteration, products nondecreasing,
+    # the last record holds the converged pairs
+    h = stats["history"]
+    assert len(h) == stats["iterations"]
+    assert all(h[i]["n_mvm"] < h[i + 1]["n_mvm"] for i in range(len(h) - 1))
+    assert h[-1]["n_mvm"] == stats["n_mvm"]
+    assert h[-1]["n_converged"] + h[-1]["n_locked"] == 4
+    assert h[-1]["r_max_accepted"] <= 1e-9 and h[0]["r_min"] > 1e-9
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
