@@ -461,6 +461,26 @@ typedef struct {
                                 vector from `seed`), checked against every
                                 Rayleigh quotient with a fallback to
                                 Gershgorin */
+    int adapt;               /* 1: re-select the degree after the first filter
+                                pass from the density of states that pass
+                                measures (the 2 n_p + 1 Chebyshev moments of
+                                the random start block, Sec. 4): N_T by Eq.
+                                DOS:target, the search margin for n_s by Eq.
+                                DOS:search, then the eta-minimising n_p
+                                (Sec. 2.3-2.4) for the remaining iterations
+                                (gamma_corr is then dropped).  0 (default):
+                                keep n_p.  The moment partial sums use the
+                                context's scratch memory. */
+    int harmonic;            /* 1 (with lock = 1): step 7 extracts harmonic
+                                Ritz pairs for the target at the window centre
+                                (the refinement of the step 7 remarks and
+                                Sec. 6) instead of Ritz pairs: the Petrov-
+                                Galerkin pairs of (H - tau) against
+                                (H - tau) X, ranked by their Rayleigh
+                                quotients; converged ones are locked as an
+                                orthonormal basis with the Ritz pairs of H
+                                inside it.  One more Gram (of H X) per
+                                iteration.  0 (default): Ritz pairs. */
 } chebfd_params;
 
 typedef struct {
@@ -473,6 +493,9 @@ typedef struct {
     double a, b;
     double t_total, t_filter, t_ortho, t_rr;   /* seconds */
     double max_residual;
+    int n_p_used;            /* filter degree of the last iteration */
+    double n_t_estimate;     /* adapt = 1: KPM count of the window (Eq.
+                                DOS:target) from the first pass; else 0 */
 } chebfd_stats;
 
 /* Fills `p` with defaults: Lanczos kernel mu = 2, eps 1e-9, max_iter 50, C128,
@@ -504,7 +527,7 @@ int chebfd_result_destroy(chebfd_result *r);
  * the matrix-vector products so far (sum of active columns times n_p), the
  * phase's precision, the pairs locked before the iteration, the in-window
  * Ritz pairs with residual <= eps (converged) and <= sqrt(eps) (accepted,
- * i.e. not ghosts), the smallest residual of an in-window Ritz pair and the
+ * i.e. not ghosts) and all in-window pairs of the block, the smallest residual of an in-window Ritz pair and the
  * largest residual of an accepted or locked one (NaN if none).  After a
  * restart on the Gershgorin interval the history is the restarted run's. */
 typedef struct {
@@ -513,6 +536,8 @@ typedef struct {
     int n_locked;
     int n_converged;
     int n_accepted;
+    int n_window;            /* in-window Ritz pairs of the block (accepted
+                                ones and ghosts) */
     double r_min;
     double r_max_accepted;
 } chebfd_iter_info;

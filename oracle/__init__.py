@@ -79,8 +79,10 @@ def lib():
         L.orc_svqb.argtypes = [i64, vp, vp, i64, dbl, u64, u64]
         L.orc_rayleigh_ritz.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, vp, vp]
         L.orc_chebfd_solve.restype = i32
+        L.orc_harmonic_ritz.restype = i32
+        L.orc_harmonic_ritz.argtypes = [i64, vp, vp, vp, vp, vp, vp, i64, dbl, vp, vp]
         L.orc_chebfd_solve.argtypes = [i64, vp, vp, vp, dbl, dbl, i64, i32, i32, dbl, dbl, i32,
-                                       u64, dbl, dbl, vp, vp, vp, vp]
+                                       u64, dbl, dbl, vp, vp, vp, vp, i32]
         L.orc_num_threads.restype = i32
         _lib = L
     return _lib
@@ -406,22 +408,39 @@ def rayleigh_ritz(H: CSR, Y):
     return th, Y, res
 
 
+def harmonic_ritz(H: CSR, Y, tau):
+    """Harmonic Ritz pairs of span(Y) (Y orthonormal) for the target tau:
+    (rho ascending, unit vectors, residuals); see orc_harmonic_ritz."""
+    Y = np.array(Y, np.complex128, order="C", copy=True)
+    W = np.empty_like(Y)
+    T = np.empty_like(Y)
+    ns = Y.shape[1]
+    rho = np.empty(ns)
+    res = np.empty(ns)
+    if lib().orc_harmonic_ritz(H.n, *H.ptrs(), _p(Y), _p(W), _p(T), ns, tau, _p(rho), _p(res)):
+        raise ValueError("orc_harmonic_ritz: (H - tau) Y is rank deficient")
+    return rho, Y, res
+
+
 class _Stats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("n_found", C.c_int), ("n_mvm", C.c_int64),
                 ("refilled", C.c_int), ("a", C.c_double), ("b", C.c_double)]
 
 
 def chebfd_solve(H: CSR, lam_lo, lam_hi, n_s, n_p, kind="lanczos", mu=2.0, eps=1e-9,
-                 max_iter=50, seed=1, a=float("nan"), b=float("nan"), vectors=True):
-    """The ChebFD scheme of Sec. 3.1 (steps 1-8).  Returns
-    (status, evals, residuals, evecs or None, stats dict)."""
+                 max_iter=50, seed=1, a=float("nan"), b=float("nan"), vectors=True,
+                 harmonic=False):
+    """The ChebFD scheme of Sec. 3.1 (steps 1-8), optionally with harmonic
+    Ritz extraction in step 7.  Returns (status, evals, residuals, evecs or
+    None, stats dict)."""
     ev = np.empty(n_s)
     rs = np.empty(n_s)
     V = np.empty((H.n, n_s), np.complex128) if vectors else None
     st = _Stats()
     status = lib().orc_chebfd_solve(H.n, *H.ptrs(), lam_lo, lam_hi, n_s, n_p,
                                     KERNELS[kind] if isinstance(kind, str) else kind, mu, eps,
-                                    max_iter, seed, a, b, _p(ev), _p(rs), _p(V), C.byref(st))
+                                    max_iter, seed, a, b, _p(ev), _p(rs), _p(V), C.byref(st),
+                                    1 if harmonic else 0)
     if status < 0:
         raise ValueError("orc_chebfd_solve: invalid arguments")
     f = st.n_found

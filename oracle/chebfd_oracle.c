@@ -583,6 +583,127 @@ void orc_rayleigh_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, con
     free(G); free(Uv);
 }
 
+/* Harmonic Ritz extraction (Sec. 3.1 step 7 remarks, Sec. 6: the cleaner
+ * alternative to Ritz values for interior eigenvalues; Morgan 1991, Paige,
+ * Parlett and van der Vorst 1995).  For the orthonormal block Y and the
+ * target tau, a harmonic Ritz pair (theta, Y s) satisfies the Petrov-Galerkin
+ * condition
+ *     (H - tau) Y s - (theta - tau) Y s  orthogonal to  (H - tau) Y,
+ * i.e. M s = (theta - tau) A s with A = Y^H (H - tau) Y (Hermitian) and
+ * M = ((H - tau) Y)^H ((H - tau) Y) (positive definite).  With the Cholesky
+ * factor M = L L^H and z = L^H s this is the Hermitian problem
+ *     L^{-1} A L^{-H} z = z / (theta - tau),
+ * solved by the cyclic Jacobi method; s = L^{-H} z.  The vectors y = Y s /
+ * |s| (|Y s| = |s|) carry the eigenvalue estimate rho = y^H H y (the Rayleigh
+ * quotient), by which the pairs are returned in ascending order, with the
+ * residuals |H y - rho y|.  Y and W (W = H Y on return) are overwritten by
+ * the vectors and their images.  Returns -1 if M is not numerically
+ * positive definite (tau an eigenvalue with its vector in span Y). */
+int orc_harmonic_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, const cplx *val,
+                      cplx *Y, cplx *W, cplx *Tmp, int64_t n_s, double tau, double *rho,
+                      double *res)
+{
+    int ns = (int)n_s, rc = 0;
+    size_t blk = (size_t)(n * n_s);
+    cplx *G = (cplx *)malloc(sizeof(cplx) * ns * ns);
+    cplx *M = (cplx *)malloc(sizeof(cplx) * ns * ns);
+    cplx *L = (cplx *)calloc((size_t)ns * ns, sizeof(cplx));
+    cplx *Li = (cplx *)calloc((size_t)ns * ns, sizeof(cplx));
+    cplx *Cm = (cplx *)malloc(sizeof(cplx) * ns * ns);
+    cplx *Z = (cplx *)malloc(sizeof(cplx) * ns * ns);
+    cplx *S = (cplx *)malloc(sizeof(cplx) * ns * ns);
+    double *zeta = (double *)malloc(sizeof(double) * ns);
+    int *ord = (int *)malloc(sizeof(int) * ns);
+    orc_spmm(n, rowptr, col, val, Y, W, n_s);
+    /* G = Y^H H Y, Hermitian part; M from the block (H - tau) Y */
+    orc_gram_kahan(n, Y, n_s, W, n_s, G);
+    for (int k = 0; k < ns; ++k)
+        for (int l = k; l < ns; ++l) {
+            cplx v = 0.5 * (G[k * ns + l] + conj(G[l * ns + k]));
+            G[k * ns + l] = v; G[l * ns + k] = conj(v);
+        }
+    for (size_t i = 0; i < blk; ++i) Tmp[i] = W[i] - tau * Y[i];
+    orc_gram_kahan(n, Tmp, n_s, Tmp, n_s, M);
+    /* Cholesky M = L L^H (lower) */
+    for (int j = 0; j < ns && rc == 0; ++j) {
+        double d = creal(M[j * ns + j]);
+        for (int q = 0; q < j; ++q) d -= creal(L[j * ns + q] * conj(L[j * ns + q]));
+        if (!(d > 0.0)) { rc = -1; break; }
+        L[j * ns + j] = sqrt(d);
+        for (int i = j + 1; i < ns; ++i) {
+            cplx v = M[i * ns + j];
+            for (int q = 0; q < j; ++q) v -= L[i * ns + q] * conj(L[j * ns + q]);
+            L[i * ns + j] = v / L[j * ns + j];
+        }
+    }
+    if (rc == 0) {
+        /* Li = L^{-1} by forward substitution */
+        for (int c = 0; c < ns; ++c) {
+            Li[c * ns + c] = 1.0 / L[c * ns + c];
+            for (int i = c + 1; i < ns; ++i) {
+                cplx v = 0.0;
+                for (int q = c; q < i; ++q) v += L[i * ns + q] * Li[q * ns + c];
+                Li[i * ns + c] = -v / L[i * ns + i];
+            }
+        }
+        /* C = Li (G - tau I) Li^H */
+        for (int i = 0; i < ns; ++i)
+            for (int j = 0; j < ns; ++j) {
+                cplx v = 0.0;
+                for (int p = 0; p < ns; ++p)
+                    for (int q = 0; q < ns; ++q) {
+                        cplx a = G[p * ns + q] - (p == q ? tau : 0.0);
+                        v += Li[i * ns + p] * a * conj(Li[j * ns + q]);
+                    }
+                Cm[i * ns + j] = v;
+            }
+        orc_jacobi_herm(ns, Cm, zeta, Z);
+        /* S = Li^H Z, unit columns; rho_j = s_j^H G s_j */
+        for (int i = 0; i < ns; ++i)
+            for (int j = 0; j < ns; ++j) {
+                cplx v = 0.0;
+                for (int q = 0; q < ns; ++q) v += conj(Li[q * ns + i]) * Z[q * ns + j];
+                S[i * ns + j] = v;
+            }
+        for (int j = 0; j < ns; ++j) {
+            double nrm = 0.0;
+            for (int i = 0; i < ns; ++i) nrm += creal(S[i * ns + j] * conj(S[i * ns + j]));
+            nrm = sqrt(nrm);
+            for (int i = 0; i < ns; ++i) S[i * ns + j] /= nrm;
+            cplx r = 0.0;
+            for (int p = 0; p < ns; ++p)
+                for (int q = 0; q < ns; ++q) r += conj(S[p * ns + j]) * G[p * ns + q] * S[q * ns + j];
+            zeta[j] = creal(r);
+        }
+        /* ascending rho: a permutation of the columns of S */
+        for (int j = 0; j < ns; ++j) ord[j] = j;
+        for (int j = 1; j < ns; ++j) {
+            int o = ord[j], q = j - 1;
+            while (q >= 0 && zeta[ord[q]] > zeta[o]) { ord[q + 1] = ord[q]; --q; }
+            ord[q + 1] = o;
+        }
+        for (int j = 0; j < ns; ++j) {
+            rho[j] = zeta[ord[j]];
+            for (int i = 0; i < ns; ++i) Z[i * ns + j] = S[i * ns + ord[j]];
+        }
+        orc_block_times_small(n, Y, n_s, Z, n_s, Tmp);
+        memcpy(Y, Tmp, sizeof(cplx) * blk);
+        orc_block_times_small(n, W, n_s, Z, n_s, Tmp);
+        memcpy(W, Tmp, sizeof(cplx) * blk);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ns; ++k) {
+            double s2 = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                cplx r = W[i * n_s + k] - rho[k] * Y[i * n_s + k];
+                s2 += creal(r * conj(r));
+            }
+            res[k] = sqrt(s2);
+        }
+    }
+    free(G); free(M); free(L); free(Li); free(Cm); free(Z); free(S); free(zeta); free(ord);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The ChebFD scheme, Sec. 3.1 steps 1-8.                                     */
 /* Readings where the paper leaves a choice:                                 */
@@ -597,6 +718,8 @@ void orc_rayleigh_ritz(int64_t n, const int64_t *rowptr, const int32_t *col, con
 /*    from the previous iteration (a ghost's residual is large and does     */
 /*    not decrease, step 7 remarks).  No tolerance factor is applied;       */
 /*  - the restart block is the full set of n_s Ritz vectors (step 8b).      */
+/* With harmonic != 0 step 7 extracts harmonic Ritz pairs for the target at */
+/* the window centre (orc_harmonic_ritz) instead of Ritz pairs.             */
 /* Outputs the converged in-window pairs in ascending order.                 */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -611,7 +734,7 @@ int orc_chebfd_solve(int64_t n, const int64_t *rowptr, const int32_t *col, const
                      double lam_lo, double lam_hi, int64_t n_s, int n_p, int kernel, double mu,
                      double eps, int max_iter, uint64_t seed, double a, double b,
                      double *evals_out, double *res_out, cplx *evecs_out /* n x n_s, nullable */,
-                     orc_solve_stats *st)
+                     orc_solve_stats *st, int harmonic)
 {
     if (!(lam_lo < lam_hi) || n_p < 2 || n_s < 1) return -1;
     if (isnan(a) || isnan(b)) orc_gershgorin(n, rowptr, col, val, &a, &b);
@@ -632,7 +755,10 @@ int orc_chebfd_solve(int64_t n, const int64_t *rowptr, const int32_t *col, const
     for (it = 1; it <= max_iter; ++it) {
         orc_filter(n, rowptr, col, val, a, b, gam, n_p, X, U, W, n_s, NULL);
         refilled += orc_svqb(n, X, U, n_s, 1e-12, seed, (uint64_t)it * 64u * (uint64_t)blk);
-        orc_rayleigh_ritz(n, rowptr, col, val, X, W, U, n_s, theta, res);
+        if (!harmonic ||
+            orc_harmonic_ritz(n, rowptr, col, val, X, W, U, n_s, 0.5 * (lam_lo + lam_hi), theta,
+                              res) != 0)
+            orc_rayleigh_ritz(n, rowptr, col, val, X, W, U, n_s, theta, res);
         int nconving = 0;
         double rmin = INFINITY;
         nconv = 0;

@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("max_iter", C.c_int), ("precision", C.c_int), ("lock", C.c_int),
                 ("a", C.c_double), ("b", C.c_double), ("seed", C.c_uint64),
                 ("gamma_corr", C.c_void_p), ("polish_switch", C.c_double), ("vectors", C.c_int),
-                ("verbose", C.c_int), ("bounds", C.c_int)]
+                ("verbose", C.c_int), ("bounds", C.c_int), ("adapt", C.c_int),
+                ("harmonic", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -41,7 +42,7 @@ class Stats(C.Structure):
                 ("n_locked", C.c_int), ("refilled", C.c_int), ("n_mvm", C.c_int64),
                 ("a", C.c_double), ("b", C.c_double), ("t_total", C.c_double),
                 ("t_filter", C.c_double), ("t_ortho", C.c_double), ("t_rr", C.c_double),
-                ("max_residual", C.c_double)]
+                ("max_residual", C.c_double), ("n_p_used", C.c_int), ("n_t_estimate", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -49,8 +50,8 @@ class Stats(C.Structure):
 
 class IterInfo(C.Structure):
     _fields_ = [("n_mvm", C.c_int64), ("precision", C.c_int), ("n_locked", C.c_int),
-                ("n_converged", C.c_int), ("n_accepted", C.c_int), ("r_min", C.c_double),
-                ("r_max_accepted", C.c_double)]
+                ("n_converged", C.c_int), ("n_accepted", C.c_int), ("n_window", C.c_int),
+                ("r_min", C.c_double), ("r_max_accepted", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -60,7 +60,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t blk64 = 0, blk32 = 0;   // bytes of one c128 / c64 block
     size_t off_b[4] = {0, 0, 0, 0};
-    size_t off_x32 = 0, off_q = 0, off_small = 0, total = 0;
+    size_t off_x32 = 0, off_q = 0, off_mom = 0, off_small = 0, total = 0;
     size_t small = 0;
 };
 
@@ -86,6 +86,11 @@ Layout layout(int64_t n, const chebfd_params &p)
         L.off_q = off;
         off += L.blk64;
     }
+    if (p.adapt) {
+        // Chebyshev moments of the first filter pass, (2 n_p + 1) x n_s
+        L.off_mom = off;
+        off += align256((size_t)(2 * p.n_p + 1) * p.n_s * 8);
+    }
     // small device matrices: S (n_s^2 c128), Tr (4 n_s^2 doubles), theta,
     // residuals (n_s each), column index list (n_s int32)
     const size_t ns = (size_t)p.n_s;
@@ -95,6 +100,89 @@ Layout layout(int64_t n, const chebfd_params &p)
     off += L.small;
     L.total = off;
     return L;
+}
+
+// Harmonic Ritz extraction (Sec. 3.1 step 7 remarks, Sec. 6) for the
+// target tau from G = X^H H X and Mu = (H X)^H (H X) of an orthonormal X:
+// M = ((H - tau) X)^H ((H - tau) X) = Mu - tau (G + G^H) + tau^2 I, the
+// Petrov-Galerkin pairs solve M s = (theta - tau) (G - tau I) s, i.e. the
+// Hermitian problem T^H (G - tau I) T z = z / (theta - tau) with T = L^{-H}
+// for M = L L^H, s = T z.  Returns the coefficient matrix S (k x k,
+// interleaved, row-major) with unit columns ordered by their Rayleigh
+// quotients rho_j = s_j^H G s_j (ascending), or -1 if M is not positive
+// definite.
+int harmonic_extract(int k, const std::vector<double> &G, const std::vector<double> &Mu, double tau,
+                     std::vector<double> &Sout, std::vector<double> &rho)
+{
+    typedef std::complex<double> cd;
+    auto at = [&](const std::vector<double> &A, int i, int j) {
+        return cd(A[2 * ((size_t)i * k + j)], A[2 * ((size_t)i * k + j) + 1]);
+    };
+    std::vector<cd> Gh((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) Gh[(size_t)i * k + j] = 0.5 * (at(G, i, j) + std::conj(at(G, j, i)));
+    std::vector<double> M((size_t)2 * k * k), T;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            const cd gsym = Gh[(size_t)i * k + j] + std::conj(Gh[(size_t)j * k + i]);
+            cd v = 0.5 * (at(Mu, i, j) + std::conj(at(Mu, j, i))) - tau * gsym;
+            if (i == j) v += tau * tau;
+            M[2 * ((size_t)i * k + j)] = v.real();
+            M[2 * ((size_t)i * k + j) + 1] = v.imag();
+        }
+    if (chol_inv_factor(k, M, T) != 0) return -1;
+    auto Tat = [&](int i, int j) { return cd(T[2 * ((size_t)i * k + j)], T[2 * ((size_t)i * k + j) + 1]); };
+    // C = T^H (G - tau I) T
+    std::vector<cd> AT((size_t)k * k, cd(0.0));
+    for (int i = 0; i < k; ++i)
+        for (int q = 0; q < k; ++q) {
+            const cd a = Gh[(size_t)i * k + q] - (i == q ? tau : 0.0);
+            if (a == cd(0.0)) continue;
+            for (int j = q; j < k; ++j) AT[(size_t)i * k + j] += a * Tat(q, j);   // T upper
+        }
+    std::vector<double> Cm((size_t)2 * k * k), zeta;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            cd v = 0.0;
+            for (int p = 0; p <= i; ++p) v += std::conj(Tat(p, i)) * AT[(size_t)p * k + j];
+            Cm[2 * ((size_t)i * k + j)] = v.real();
+            Cm[2 * ((size_t)i * k + j) + 1] = v.imag();
+        }
+    if (herm_eig(k, Cm, zeta) != 0) return -1;
+    // S = T Z, unit columns, Rayleigh quotients
+    std::vector<cd> S((size_t)k * k, cd(0.0));
+    for (int i = 0; i < k; ++i)
+        for (int q = i; q < k; ++q) {
+            const cd t = Tat(i, q);
+            for (int j = 0; j < k; ++j) S[(size_t)i * k + j] += t * at(Cm, q, j);
+        }
+    std::vector<double> r(k);
+    for (int j = 0; j < k; ++j) {
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += std::norm(S[(size_t)i * k + j]);
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < k; ++i) S[(size_t)i * k + j] /= nrm;
+        cd v = 0.0;
+        for (int p = 0; p < k; ++p) {
+            cd gs = 0.0;
+            for (int q = 0; q < k; ++q) gs += Gh[(size_t)p * k + q] * S[(size_t)q * k + j];
+            v += std::conj(S[(size_t)p * k + j]) * gs;
+        }
+        r[j] = v.real();
+    }
+    std::vector<int> ord(k);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return r[x] < r[y]; });
+    Sout.assign((size_t)2 * k * k, 0.0);
+    rho.resize(k);
+    for (int j = 0; j < k; ++j) {
+        rho[j] = r[ord[j]];
+        for (int i = 0; i < k; ++i) {
+            Sout[2 * ((size_t)i * k + j)] = S[(size_t)i * k + ord[j]].real();
+            Sout[2 * ((size_t)i * k + j) + 1] = S[(size_t)i * k + ord[j]].imag();
+        }
+    }
+    return 0;
 }
 
 struct Solver {
@@ -248,6 +336,139 @@ struct Solver {
         return CHEBFD_OK;
     }
 
+    // Adaptive degree (the refinement of Sec. 6): the first pass filtered
+    // the random start block, so its moments <x, T_m x> / <x, x>, averaged
+    // over the k columns, estimate the normalised density of states (a
+    // stochastic trace with k vectors).  N_T follows from Eq. DOS:target,
+    // the search margin for N_S from Eq. DOS:search, and the degree that
+    // minimises eta for that margin (Sec. 2.3-2.4) is used from now on.
+    int reselect_degree(const double *dmom, int ld, int k)
+    {
+        const int M = 2 * p.n_p + 1;
+        std::vector<double> m((size_t)M * ld), mu(M, 0.0);
+        int rc = down(m.data(), dmom, m.size() * 8);
+        if (rc) return rc;
+        for (int c = 0; c < k; ++c) {
+            const double m0 = m[c];
+            if (!(m0 > 0.0)) continue;
+            for (int j = 0; j < M; ++j) mu[j] += m[(size_t)j * ld + c] / m0;
+        }
+        for (int j = 0; j < M; ++j) mu[j] /= k;
+        double nt = 0.0, margin = 0.0;
+        int ns_fixed = p.n_s, np_new = 0;
+        if ((rc = chebfd_dos_params(mu.data(), M, n, a, b, p.lam_lo, p.lam_hi, 1.0, p.kernel,
+                                    p.mu, p.n_s, &nt, &ns_fixed, &np_new, &margin)))
+            return rc;
+        st.n_t_estimate = nt;
+        if (p.verbose) {
+            std::fprintf(stderr,
+                         "chebfd: adaptive degree: N_T estimate %.1f, margin %.4g, n_p %d -> %d\n",
+                         nt, margin, p.n_p, np_new);
+            std::fflush(stderr);
+        }
+        if (np_new >= 2 && np_new != p.n_p) {
+            p.n_p = np_new;
+            gamma.assign(p.n_p + 1, 0.0);
+            if ((rc = chebfd_coeffs(p.lam_lo, p.lam_hi, a, b, p.n_p, p.kernel, p.mu, gamma.data())))
+                return rc;
+        }
+        return CHEBFD_OK;
+    }
+
+    std::vector<double> Gk, Sh;   // harmonic mode: X^H H X and the coefficients
+
+    // Locks the converged harmonic Ritz vectors (columns conv of X, their H
+    // images in W, coefficients Sh in the orthonormal basis of this
+    // iteration, whose Rayleigh matrix is Gk): an orthonormal basis of them
+    // by the Cholesky factor of their Gram Sc^H Sc, then the Ritz pairs of H
+    // inside that space; the locked residuals are recomputed on the device.
+    // U is scratch.
+    int lock_harmonic(void *X, void *U, void *W, void *Q, int n_lock, const std::vector<int> &conv,
+                      std::vector<double> &lock_vals, std::vector<double> &lock_res)
+    {
+        typedef std::complex<double> cd;
+        const int k = (int)std::sqrt((double)(Sh.size() / 2) + 0.5), c = (int)conv.size();
+        auto sh = [&](int i, int j) {
+            return cd(Sh[2 * ((size_t)i * k + j)], Sh[2 * ((size_t)i * k + j) + 1]);
+        };
+        auto gk = [&](int i, int j) {
+            return cd(Gk[2 * ((size_t)i * k + j)], Gk[2 * ((size_t)i * k + j) + 1]);
+        };
+        std::vector<double> Gc((size_t)2 * c * c), Tc;
+        std::vector<cd> HcS((size_t)c * c, cd(0.0));
+        for (int a = 0; a < c; ++a)
+            for (int b = 0; b < c; ++b) {
+                cd g = 0.0, h = 0.0;
+                for (int i = 0; i < k; ++i) {
+                    g += std::conj(sh(i, conv[a])) * sh(i, conv[b]);
+                    cd gs = 0.0;
+                    for (int q = 0; q < k; ++q) gs += gk(i, q) * sh(q, conv[b]);
+                    h += std::conj(sh(i, conv[a])) * gs;
+                }
+                Gc[2 * ((size_t)a * c + b)] = g.real();
+                Gc[2 * ((size_t)a * c + b) + 1] = g.imag();
+                HcS[(size_t)a * c + b] = h;
+            }
+        if (chol_inv_factor(c, Gc, Tc) != 0)
+            return fail(CHEBFD_ERR_NONFINITE, "harmonic locking: converged vectors are dependent");
+        auto tc = [&](int i, int j) {
+            return cd(Tc[2 * ((size_t)i * c + j)], Tc[2 * ((size_t)i * c + j) + 1]);
+        };
+        // Hc = Tc^H HcS Tc, Hermitian; its eigenvectors rotate the basis
+        std::vector<double> Hc((size_t)2 * c * c), vals;
+        for (int a = 0; a < c; ++a)
+            for (int b = 0; b < c; ++b) {
+                cd v = 0.0;
+                for (int p = 0; p < c; ++p)
+                    for (int q = 0; q < c; ++q) v += std::conj(tc(p, a)) * HcS[(size_t)p * c + q] * tc(q, b);
+                Hc[2 * ((size_t)a * c + b)] = v.real();
+                Hc[2 * ((size_t)a * c + b) + 1] = v.imag();
+            }
+        for (int a = 0; a < c; ++a)
+            for (int b = a + 1; b < c; ++b) {   // exact Hermitian symmetry
+                const double re = 0.5 * (Hc[2 * ((size_t)a * c + b)] + Hc[2 * ((size_t)b * c + a)]);
+                const double im = 0.5 * (Hc[2 * ((size_t)a * c + b) + 1] - Hc[2 * ((size_t)b * c + a) + 1]);
+                Hc[2 * ((size_t)a * c + b)] = re;
+                Hc[2 * ((size_t)a * c + b) + 1] = im;
+                Hc[2 * ((size_t)b * c + a)] = re;
+                Hc[2 * ((size_t)b * c + a) + 1] = -im;
+            }
+        if (herm_eig(c, Hc, vals) != 0)
+            return fail(CHEBFD_ERR_NONFINITE, "harmonic locking: eigensolver failed");
+        // R = Tc Zc (c x c): locked = X_conv R, their images = W_conv R
+        std::vector<double> R((size_t)2 * c * c, 0.0);
+        for (int a = 0; a < c; ++a)
+            for (int b = 0; b < c; ++b) {
+                cd v = 0.0;
+                for (int q = 0; q < c; ++q)
+                    v += tc(a, q) * cd(Hc[2 * ((size_t)q * c + b)], Hc[2 * ((size_t)q * c + b) + 1]);
+                R[2 * ((size_t)a * c + b)] = v.real();
+                R[2 * ((size_t)a * c + b) + 1] = v.imag();
+            }
+        int rc;
+        std::vector<int32_t> idx(conv.begin(), conv.end());
+        if ((rc = up(dIdx, idx.data(), idx.size() * 4))) return rc;
+        if ((rc = upload_T(R, c, c))) return rc;
+        void *Qs = (char *)Q + (size_t)n_lock * 16;
+        if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, X, ns, U, ns, 0, dIdx, n, c))) return rc;
+        if ((rc = launch_block_times(ctx, CHEBFD_PREC_C128, U, ns, n, c, dTr, c, CHEBFD_PREC_C128,
+                                     Qs, ns, 0)))
+            return rc;
+        if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, W, ns, U, ns, 0, dIdx, n, c))) return rc;
+        if ((rc = launch_block_times(ctx, CHEBFD_PREC_C128, U, ns, n, c, dTr, c, CHEBFD_PREC_C128,
+                                     W, ns, 0)))
+            return rc;
+        if ((rc = up(dTheta, vals.data(), (size_t)c * 8))) return rc;
+        if ((rc = launch_residuals(ctx, CHEBFD_PREC_C128, Qs, W, n, c, ns, dTheta, dRes))) return rc;
+        std::vector<double> r(c);
+        if ((rc = down(r.data(), dRes, (size_t)c * 8))) return rc;
+        for (int a = 0; a < c; ++a) {
+            lock_vals.push_back(vals[a]);
+            lock_res.push_back(r[a]);
+        }
+        return CHEBFD_OK;
+    }
+
     int run(chebfd_result *out)
     {
         const auto t0 = clk::now();
@@ -296,17 +517,22 @@ struct Solver {
             if (k <= 0) break;
             // ---------------- step 5: filter
             auto ta = clk::now();
+            // the first pass of an adaptive solve also returns the moments
+            double *mom = (p.adapt && it == 1) ? (double *)(base + L.off_mom) : nullptr;
             if (prec == CHEBFD_PREC_C64) {
                 rc = filter_apply(ctx, H, CHEBFD_PREC_C64, gamma.data(), p.n_p, a, b, X32, U32,
-                                  W32, k & 1 ? k + 1 : k, ns, nullptr, p.verbose ? 1024 : 0);
+                                  W32, k & 1 ? k + 1 : k, ns, mom, p.verbose ? 1024 : 0);
                 ++st.iterations_c64;
             } else {
                 rc = filter_apply(ctx, H, CHEBFD_PREC_C128, gamma.data(), p.n_p, a, b, X, U, W, k,
-                                  ns, nullptr, p.verbose ? 1024 : 0);
+                                  ns, mom, p.verbose ? 1024 : 0);
             }
             if (rc) return rc;
             st.n_mvm += (int64_t)k * p.n_p;
             if ((rc = sync())) return rc;
+            if (mom && (rc = reselect_degree(mom, k & 1 && prec == CHEBFD_PREC_C64 ? k + 1 : k,
+                                             k)))
+                return rc;
             auto tb = clk::now();
             st.t_filter += secs(ta, tb);
             // ---------------- step 6: orthogonalise (FP64 on the converted block)
@@ -332,7 +558,16 @@ struct Solver {
             s.s_u = 0.0;
             if ((rc = launch_step(ctx, H, s, nullptr))) return rc;        // U = H X
             if ((rc = gram_host(CHEBFD_PREC_C128, X, k, CHEBFD_PREC_C128, U, k, S))) return rc;
-            if (herm_eig(k, S, theta) != 0) {
+            bool harm = false;
+            if (p.harmonic) {
+                // harmonic Ritz pairs for the window centre (one more Gram)
+                std::vector<double> Mu;
+                if ((rc = gram_host(CHEBFD_PREC_C128, U, k, CHEBFD_PREC_C128, U, k, Mu))) return rc;
+                Gk = S;
+                harm = harmonic_extract(k, S, Mu, 0.5 * (p.lam_lo + p.lam_hi), Sh, theta) == 0;
+                if (harm) S = Sh;
+            }
+            if (!harm && herm_eig(k, S, theta) != 0) {
                 if (bounds_checked) return RESTART_WIDER;
                 return fail(CHEBFD_ERR_NONFINITE, "Rayleigh-Ritz eigensolver failed");
             }
@@ -394,6 +629,7 @@ struct Solver {
                 h.r_max_accepted = 0.0;
                 for (int j = 0; j < k; ++j)
                     if (theta[j] >= p.lam_lo && theta[j] <= p.lam_hi) {
+                        ++h.n_window;
                         h.r_min = std::min(h.r_min, res[j]);
                         if (res[j] <= seps) h.r_max_accepted = std::max(h.r_max_accepted, res[j]);
                     }
@@ -519,7 +755,23 @@ struct Solver {
                 }
                 continue;
             }
-            if (p.lock && !conv_idx.empty()) {
+            if (p.lock && !conv_idx.empty() && harm) {
+                // harmonic Ritz vectors need not be orthogonal (inside a
+                // cluster or degenerate pair): lock an orthonormal basis of
+                // the converged ones, with the Ritz pairs of H inside it
+                if ((rc = lock_harmonic(X, U, W, Q, n_lock, conv_idx, lock_vals, lock_res)))
+                    return rc;
+                n_lock += (int)conv_idx.size();
+                if (!keep_idx.empty()) {
+                    std::vector<int32_t> kid(keep_idx.begin(), keep_idx.end());
+                    if ((rc = up(dIdx, kid.data(), kid.size() * 4))) return rc;
+                    if ((rc = launch_gather_cols(ctx, CHEBFD_PREC_C128, X, ns, U, ns, 0, dIdx, n,
+                                                 (int64_t)kid.size())))
+                        return rc;
+                    if ((rc = sync())) return rc;
+                    std::swap(X, U);
+                }
+            } else if (p.lock && !conv_idx.empty()) {
                 // Q[:, n_lock + j] = V[:, conv_j]; compact the rest into U
                 std::vector<int32_t> idx(conv_idx.begin(), conv_idx.end());
                 if ((rc = up(dIdx, idx.data(), idx.size() * 4))) return rc;
@@ -619,6 +871,7 @@ struct Solver {
         }
         st.n_found = nf;
         st.n_locked = n_lock;
+        st.n_p_used = p.n_p;
         st.a = a;
         st.b = b;
         st.max_residual = maxr;
@@ -672,6 +925,10 @@ static int check_params(const chebfd_matrix *H, const chebfd_params *p)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: the c64 form needs an even n_s");
     if (p->bounds < 0 || p->bounds == 1 || p->bounds > 1000)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: bounds must be 0 (Gershgorin) or 2..1000 Lanczos steps");
+    if (p->adapt != 0 && p->adapt != 1)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: adapt must be 0 or 1");
+    if (p->harmonic != 0 && (p->harmonic != 1 || !p->lock))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: harmonic must be 0, or 1 with lock = 1");
     return CHEBFD_OK;
 }
 
@@ -742,6 +999,7 @@ extern "C" int chebfd_solve(chebfd_ctx *ctx, const chebfd_matrix *H, const chebf
     if (rc == Solver::RESTART_WIDER) {
         // the estimated interval was too narrow: start again on Gershgorin's
         const chebfd_stats first = S.st;
+        S.p = *p;   // the adaptive degree of the first run does not carry over
         S.a = H->g_lo;
         S.b = H->g_hi;
         S.bounds_checked = false;

@@ -66,8 +66,17 @@ def run_solve(ctx, H, delta, n_s, n_p, corr=None, precision=B.PREC_C128, max_ite
                 iterations=st["iterations"])
 
 
+# sweep grid around the rule (N_S = 3 N_T, eta-optimal N_p): search spaces
+# from about 1.35 N_T (the largest lattice's ratio) to 4.5 N_T, degrees from
+# 0.6 to 1.6 times the rule's
+NS_FACTORS = (0.45, 0.7, 1.0, 1.5)
+NP_FACTORS = (0.6, 0.8, 1.0, 1.25, 1.6)
+
+
 def sweep(out_path, seeds):
-    """Plain-method sweep around the rule-based (N_S, N_p) for each seed."""
+    """Plain-method sweep around the rule-based (N_S, N_p) for each seed; the
+    label is the point with the fewest matrix-vector products (a count that
+    does not depend on the machine) among those that find every pair."""
     import torch
     ctx = B.Context(0)
     recs = []
@@ -75,21 +84,24 @@ def sweep(out_path, seeds):
         P = problem(ctx, s)
         ns0, np0 = P["ns0"], P["np0"]
         cand = []
-        for fs in (0.5, 1.0, 2.0):
+        for fs in NS_FACTORS:
             ns = int(min(NS_MAX, max(16, round(ns0 * fs / 2) * 2)))
-            for fp in (0.7, 1.0, 1.4):
+            for fp in NP_FACTORS:
                 cand.append((ns, max(8, int(round(np0 * fp)))))
-        cand = sorted(set(cand))
+        cand = sorted(set(cand) | {(ns0, np0)})
         runs = [(ns, npp, run_solve(ctx, P["H"], P["delta"], ns, npp, seed=s)) for ns, npp in cand]
         top = max(r["found"] for _, _, r in runs)
-        ok = [(r["time"], ns, npp) for ns, npp, r in runs if r["rc"] == 0 and r["found"] == top]
-        best = min(ok) if ok else min((r["time"], ns, npp) for ns, npp, r in runs)
+        ok = [(r["n_mvm"], r["time"], ns, npp) for ns, npp, r in runs
+              if r["rc"] == 0 and r["found"] == top]
+        best = (min(ok) if ok else min((r["n_mvm"], r["time"], ns, npp) for ns, npp, r in runs))[1:]
         margin = B.chebfd_dos_params(P["mu"], P["n"], P["a"], P["b"], -P["delta"], P["delta"],
                                      n_s=best[1], ns_max=NS_MAX, with_margin=True)[3]
         recs.append(dict(seed=s, W=P["W"], delta=P["delta"], a=P["a"], b=P["b"], n=P["n"],
                          feats=P["feats"], nt=P["nt"], ns0=ns0, np0=np0, best_ns=best[1],
                          best_np=best[2], best_time=best[0], found=top, margin=margin,
-                         runs=[(ns, npp, r["time"], r["found"], r["rc"]) for ns, npp, r in runs]))
+                         mvm_best=int(min(ok)[0]) if ok else -1,
+                         runs=[(ns, npp, r["time"], r["found"], r["rc"], int(r["n_mvm"]))
+                               for ns, npp, r in runs]))
         print(json.dumps(dict(seed=s, W=round(P["W"], 3), delta=round(P["delta"], 5),
                               nt=round(P["nt"], 1), found=top, ns0=ns0, np0=np0,
                               best=best[1:], t_best=round(best[0], 3),
@@ -110,11 +122,12 @@ def _save_sweep(path, recs):
              best_np=np.array([r["best_np"] for r in recs]),
              best_time=np.array([r["best_time"] for r in recs]),
              found=np.array([r["found"] for r in recs]), margin=np.array([r["margin"] for r in recs]),
+             mvm_best=np.array([r["mvm_best"] for r in recs]),
              runs=np.array(json.dumps([r["runs"] for r in recs])))
 
 
 L2_FIT = 2e-3        # amplitude penalty of the correction fit (unique, smooth targets)
-GAIN_MIN = 0.05      # a sweep point replaces the rule only if it is this much faster
+GAIN_MIN = 0.05      # a sweep point replaces the rule only if it needs this much fewer products
 
 
 def rule_margin(feats, n, a, b, delta, n_s):
@@ -132,8 +145,8 @@ def fitted_corrections(a, b, delta, margin, n_p, iters=120):
 
 def fit_targets(out_path, inputs):
     """Training targets: log ratios of the sweep's best (N_p, N_S) to the
-    rule where the best is at least GAIN_MIN faster (else 0: keep the
-    rule), and the hat amplitudes that minimise the damping factor of the
+    rule where the best needs at least GAIN_MIN fewer matrix-vector products
+    (else 0: keep the rule), and the hat amplitudes that minimise the damping factor of the
     rule's filter for the rule's search interval (fitted on the host, one
     thread per sample)."""
     from concurrent.futures import ThreadPoolExecutor
@@ -152,8 +165,8 @@ def fit_targets(out_path, inputs):
         amps = list(ex.map(one, range(m)))
     T = np.zeros((m, 2 + N_HAT), np.float32)
     for i in range(m):
-        t_rule = [t for ns, npp, t, f, rc in runs[i] if ns == cat["ns0"][i] and npp == cat["np0"][i]]
-        if t_rule and cat["best_time"][i] < (1.0 - GAIN_MIN) * t_rule[0]:
+        m_rule = [r[5] for r in runs[i] if r[0] == cat["ns0"][i] and r[1] == cat["np0"][i]]
+        if m_rule and 0 < cat["mvm_best"][i] < (1.0 - GAIN_MIN) * m_rule[0]:
             T[i, 0] = np.log(cat["best_np"][i] / cat["np0"][i])
             T[i, 1] = np.log(cat["best_ns"][i] / cat["ns0"][i])
     T[:, 2:] = np.stack(amps)

@@ -2,6 +2,7 @@
 Fig. fig:ConvTopi and Fig. fig:EffortTopi).
 
     python -m paper_1510_04895_amd.ti_experiment OUT.json [--part grid,kernels]
+        [--cases NS:NP:KERNEL:MU,...]
 
 Eq. (Ham) on a 256 x 256 x 10 slab (periodic x, y; open z; D = 2,621,440),
 t = 1, disorder V_n uniform in [-1, 1] (V = 2), spectral interval fixed at
@@ -19,7 +20,7 @@ N_MVM = N_p x N_S x iterations.
            against N_MVM).
 
 The disorder realisation is this build's (seed 1), so N_T differs from the
-paper's 144; the KPM estimate of Eq. DOS:target (256 moments of 16
+paper's 144; the KPM estimate of Eq. DOS:target (2048 moments of 16
 random-phase vectors) is reported beside the converged count, and the
 linear-DOS effort estimate of Eq. (etanlinear) -- eta_opt(delta') N_S
 (-log10 eps) with delta' = delta (sqrt(N_S/N_T) - 1), minimised over N_S --
@@ -61,8 +62,9 @@ def solve(ctx, H, n_s, n_p, kernel, mu, seed=1, max_iter=40):
     return dict(n_s=n_s, n_p=n_p, kernel=kernel, mu=mu, status=int(rc), time_s=round(T, 2),
                 iterations=st["iterations"], n_mvm=int(st["iterations"] * n_s * n_p),
                 n_found=int(ev.size), max_residual=float(rs.max()) if rs.size else None,
-                history=[{k: h[k] for k in ("n_mvm", "n_accepted", "n_converged", "r_min",
-                                            "r_max_accepted")} for h in st["history"]]), ev
+                history=[{k: h[k] for k in ("n_mvm", "n_window", "n_accepted", "n_converged",
+                                            "n_locked", "r_min", "r_max_accepted")}
+                         for h in st["history"]]), ev
 
 
 def theory_min(n_t):
@@ -82,13 +84,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--part", default="grid,kernels")
+    ap.add_argument("--cases", default="",
+                    help="explicit runs NS:NP:KERNEL:MU (comma separated) instead of --part")
     args = ap.parse_args()
     ctx = B.Context(0)
     H = B.Matrix.ti(ctx, L, pbc=3, V=V, seed=1, storage=B.STORAGE_STENCIL)
     info = H.info()
     n = info["n"]
     lo, hi = B.chebfd_lanczos_bounds(ctx, H, k=60, seed=1, pad=0.0)
-    mu_k = B.chebfd_kpm_moments(ctx, H, 16, 256, 7, A, BB, precision=B.PREC_C128)
+    mu_k = B.chebfd_kpm_moments(ctx, H, 16, 2048, 7, A, BB, precision=B.PREC_C128)
     nt_kpm = scale_runs.kpm_count(mu_k, n, A, BB, DELTA)
     out = dict(lattice="x".join(map(str, L)), D=n, V=V, interval=[A, BB], window=[-DELTA, DELTA],
                eps=EPS, lanczos_extremes=[lo, hi], n_t_kpm_estimate=round(nt_kpm, 1),
@@ -100,8 +104,11 @@ def main():
                          "does not hold for this realisation")
     ref = None
     S_w = max(abs(A), abs(BB))
-    parts = args.part.split(",")
+    parts = args.part.split(",") if not args.cases else []
     cases = []
+    for c in filter(None, args.cases.split(",")):
+        ns, npp, k, m = c.split(":")
+        cases.append((int(ns), int(npp), k, float(m), "cases"))
     if "grid" in parts:
         cases += [(ns, npp, "lanczos", 2.0, "grid") for ns in GRID_NS for npp in GRID_NP]
     if "kernels" in parts:
@@ -112,6 +119,11 @@ def main():
         r["part"] = tag
         if ref is None and r["status"] == 0:
             ref = ev
+        # effort until every window pair had converged (the paper stops
+        # there; the exit rule runs one confirming iteration more)
+        full = [h["n_mvm"] for h in r["history"] if ref is not None and
+                h["n_converged"] + h["n_locked"] >= ref.size]
+        r["n_mvm_all_converged"] = int(full[0]) if full else None
         r["same_eigenvalues"] = bool(ref is not None and ev.size == ref.size and
                                      (ev.size == 0 or np.abs(ev - ref).max() < 1e-10 * S_w))
         out["runs"].append(r)
@@ -125,8 +137,9 @@ def main():
         out["theory_min"] = theory_min(int(ref.size))
         ok = [r for r in out["runs"] if r["status"] == 0 and r["same_eigenvalues"]]
         if ok:
-            best = min(ok, key=lambda r: r["n_mvm"])
-            out["best"] = {k: best[k] for k in ("n_s", "n_p", "kernel", "mu", "n_mvm", "iterations")}
+            best = min(ok, key=lambda r: r["n_mvm_all_converged"] or r["n_mvm"])
+            out["best"] = {k: best[k] for k in ("n_s", "n_p", "kernel", "mu", "n_mvm",
+                                                "n_mvm_all_converged", "iterations")}
         out["eigenvalues"] = [float(v) for v in ref]
     with open(args.out, "w") as fh:
         json.dump(out, fh, indent=1)

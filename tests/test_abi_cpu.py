@@ -179,3 +179,23 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "is missing" in r.stdout and "no CPU fallback" in r.stdout
+
+
+def test_dos_params_match_oracle_density(B, orc):
+    """The library's KPM count (Eq. DOS:target, a closed-form integral of the
+    Jackson-damped expansion) and search margin (Eq. DOS:search, bisection)
+    against the oracle's own density integrated by Gauss-Legendre
+    quadrature and its own bisection, on the same moments."""
+    H = orc.ti_hamiltonian(6, 6, 6, pbc=3, V=1.0, seed=2)
+    a, b = orc.gershgorin(H)
+    X = inp.random_phase_block(H.n, 24, seed=1)
+    mu = orc.moments_direct(H, a, b, X, 256).mean(1) / H.n
+    for d in (0.3, 0.8, 1.5):
+        want = orc.dos_count(mu, H.n, a, b, -d, d)
+        nt, ns, n_p = B.chebfd_dos_params(mu, H.n, a, b, -d, d, ns_over_nt=3.0)
+        assert abs(nt - want) <= 1e-8 * max(1.0, want), (d, nt, want)
+        nt2, ns2, n_p2, mg = B.chebfd_dos_params(mu, H.n, a, b, -d, d, n_s=120,
+                                                 with_margin=True)
+        mref = orc.dos_margin(mu, H.n, a, b, -d, d, 120)
+        # the library floors the margin at the kernel width 2 S_w / M
+        assert abs(mg - max(mref, (b - a) / 256)) <= 1e-9 * (b - a), (d, mg, mref)

@@ -172,3 +172,31 @@ def test_precision_form_solve_128x128x64(orc):
     assert np.abs(r - rs).max() < 1e-11
     G = V.conj().T @ V
     assert np.abs(G - np.eye(ev.size)).max() < 1e-10
+
+
+def test_adaptive_degree_full_size(env, orc):
+    """The throughput configuration with the adaptive degree, started from
+    N_p = 100: after the first pass the degree is re-selected from the
+    256-vector density estimate, and the solve returns the oracle's 64
+    window eigenvalues to 1e-10 S_w."""
+    torch, B, ctx, Hr = env
+    d = W["delta"]
+    H = _matrix(B, ctx, "stencil")
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=W["n_s"], n_p=100, kernel=W["kernel"],
+                         mu=W["mu"], eps=W["eps"], max_iter=60, lock=1, seed=W["seeds"][0],
+                         vectors=0, adapt=1)
+    rc, ev, rs, _, stats = B.chebfd_solve(ctx, H, p)
+    del H
+    torch.cuda.empty_cache()
+    gold = np.sort(_oracle_window())
+    want = gold[np.abs(gold) <= d]
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0 and ev.size == want.size, (rc, ev.size, stats)
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    # 201 moments resolve the density only to ~pi S_w / 201 = 0.13, wider than
+    # the window, so the count of a density rising away from the gap is high
+    assert 32 <= stats["n_t_estimate"] <= 128 and stats["n_p_used"] != 100, stats
+    print(f"64x64x32 adaptive: n_p 100 -> {stats['n_p_used']}, N_T estimate "
+          f"{stats['n_t_estimate']:.1f}, {stats['iterations']} iterations, "
+          f"{stats['t_total']:.2f} s")

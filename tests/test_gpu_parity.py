@@ -622,3 +622,97 @@ def test_svqb_refills_a_rank_deficient_block(env, orc):
     Hr = orc.CSR(n, rp, col, val)
     r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
     assert r.max() <= 1.05e-9
+
+
+@pytest.mark.parametrize("n_p0,prec", [(40, "c128"), (1500, "c128"), (40, "c64")])
+def test_adaptive_degree_vs_golden(env, orc, n_p0, prec):
+    """Adaptive degree (Sec. 6 refinement): from a degree far too low or far
+    too high, the first pass's moments give the window count and search
+    margin (Eq. DOS:target, Eq. DOS:search) and the eta-minimising degree
+    for N_S = 32; the solve then returns the 16 dense-oracle eigenvalues of
+    the correctness configuration.  The re-selected degree equals the rule
+    applied by the oracle's own density functions to moments of the same
+    start block (computed by the oracle), and the count estimate is within
+    the stochastic error of 16."""
+    torch, B, ctx = env
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                   "ti_8x8x8_V1_seed1_evals.txt"))
+    aw = np.sort(np.abs(gold))
+    d = 0.5 * (aw[15] + aw[16])
+    want = np.sort(gold[np.abs(gold) <= d])
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=1)
+    info = H.info()
+    S_w = max(abs(info["g_lo"]), abs(info["g_hi"]))
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=n_p0, eps=1e-9, seed=1001,
+                         max_iter=100, adapt=1,
+                         precision=B.PREC_C64 if prec == "c64" else B.PREC_C128)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    assert rc == 0 and ev.size == 16, (rc, ev, stats)
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert rs.max() <= 1e-9
+    assert stats["n_p_used"] != n_p0, stats
+    # 2 n_p0 + 1 moments resolve the density to ~pi S_w / (2 n_p0 + 1): at
+    # n_p0 = 40 that is wider than the window, and the count of a density
+    # rising away from the gap comes out high
+    if n_p0 >= 1000:
+        assert abs(stats["n_t_estimate"] - 16) <= 6, stats
+    else:
+        assert 8 <= stats["n_t_estimate"] <= 64, stats
+    if prec == "c128":
+        # the oracle's moments of the same start block (stream 1 of the seed)
+        Hr = orc.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=1)
+        a, b = orc.gershgorin(Hr)
+        X = orc.random_block(Hr.n, 32, seed=1001, stream=1, offset=0)
+        mom = orc.moments_direct(Hr, a, b, X, 2 * n_p0 + 1)
+        mu = (mom / mom[0]).mean(1)
+        nt = orc.dos_count(mu, Hr.n, a, b, -d, d)
+        assert abs(nt - stats["n_t_estimate"]) <= 1e-6 * nt
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_solve_harmonic_vs_golden(env, orc, seed):
+    """Harmonic Ritz extraction (step 7 remarks, Sec. 6) on the correctness
+    configuration: the 16 dense-oracle eigenvalues to 1e-10 S_w, residuals
+    <= 1e-9 recomputed by the oracle from the returned (orthonormal)
+    vectors; the history counts the in-window pairs, of which the ghosts
+    (in window, residual above sqrt(eps)) are reported beside those of the
+    Ritz extraction on the same start block."""
+    torch, B, ctx = env
+    w = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                f"ti_8x8x8_V1_seed{seed}_evals.txt"))
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[15] + aw[16])
+    want = np.sort(w[np.abs(w) <= d])
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=seed)
+    ghosts = {}
+    for harm in (1, 0):
+        p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=200, eps=1e-9, seed=seed + 1000,
+                             max_iter=200, harmonic=harm)
+        rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+        S_w = max(abs(stats["a"]), abs(stats["b"]))
+        assert rc == 0 and ev.size == 16, (harm, rc, ev, stats)
+        assert np.abs(ev - want).max() < 1e-10 * S_w
+        Hr = orc.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=seed)
+        r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
+        assert r.max() <= 1.05e-9
+        assert np.abs(V.conj().T @ V - np.eye(16)).max() < 1e-8
+        ghosts[harm] = [h["n_window"] - h["n_accepted"] for h in stats["history"]]
+    print(f"seed {seed}: in-window ghosts per iteration, harmonic {ghosts[1]}, Ritz {ghosts[0]}")
+
+
+def test_solve_harmonic_matches_oracle_harmonic(env, orc):
+    """The library's harmonic solve and the oracle's own harmonic solve
+    (orc_harmonic_ritz in step 7) return the same window eigenvalues of the
+    4x4x4 lattice."""
+    torch, B, ctx = env
+    Hr = orc.ti_hamiltonian(4, 4, 4, pbc=3, V=1.0, seed=1)
+    w = np.linalg.eigvalsh(Hr.dense())
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[3] + aw[4])
+    st, ev_o, _, _, so = orc.chebfd_solve(Hr, -d, d, 16, 60, eps=1e-9, seed=3, harmonic=True)
+    H = B.Matrix.ti(ctx, (4, 4, 4), pbc=3, V=1.0, seed=1)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=16, n_p=60, eps=1e-9, seed=3, harmonic=1)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    S_w = max(abs(so["a"]), abs(so["b"]))
+    assert st == 0 and rc == 0 and ev.size == ev_o.size == 4
+    assert np.abs(ev - ev_o).max() < 1e-10 * S_w

@@ -224,3 +224,59 @@ def test_solve_empty_window_returns_nothing(orc):
     st, ev, rs, V, stats = orc.chebfd_solve(H, lo, hi, 16, 60, seed=3, max_iter=20)
     assert st == 0 and ev.size == 0
     assert stats["iterations"] < 20
+
+
+def test_harmonic_ritz_petrov_galerkin_condition(orc):
+    """Harmonic Ritz pairs (Sec. 3.1 step 7 remarks, Sec. 6) of a random
+    orthonormal block Y for the target tau satisfy the defining condition,
+    written out here with numpy: for each returned unit vector y in span(Y)
+    there is a xi with P^H ((H - tau) y - xi y) = 0, P = (H - tau) Y; rho is
+    the Rayleigh quotient y^H H y, returned ascending, with the residual
+    |H y - rho y|."""
+    H = orc.ti_hamiltonian(3, 3, 4, pbc=3, V=1.0, seed=5)
+    A = H.dense()
+    g = np.random.default_rng(3)
+    Y, _ = np.linalg.qr(g.normal(size=(H.n, 12)) + 1j * g.normal(size=(H.n, 12)))
+    tau = 0.3
+    rho, V, res = orc.harmonic_ritz(H, Y, tau)
+    P = (A - tau * np.eye(H.n)) @ Y
+    # V in span(Y) and unit columns
+    assert np.abs(Y @ (Y.conj().T @ V) - V).max() < 1e-12
+    assert np.abs(np.linalg.norm(V, axis=0) - 1).max() < 1e-12
+    for j in range(V.shape[1]):
+        y = V[:, j]
+        py, pby = P.conj().T @ y, P.conj().T @ ((A - tau * np.eye(H.n)) @ y)
+        xi = np.vdot(py, pby) / np.vdot(py, py)
+        assert abs(xi.imag) < 1e-9 * abs(xi)
+        assert np.linalg.norm(pby - xi * py) <= 1e-10 * np.linalg.norm(pby)
+        assert abs(rho[j] - np.vdot(y, A @ y).real) < 1e-12
+        assert abs(res[j] - np.linalg.norm(A @ y - rho[j] * y)) < 1e-12
+    assert np.all(np.diff(rho) >= 0)
+
+
+def test_harmonic_ritz_exact_invariant_subspace(orc):
+    """On an exact invariant subspace the harmonic Ritz values are the
+    eigenvalues, whatever the target."""
+    H = orc.ti_hamiltonian(4, 4, 2, pbc=3, V=1.0, seed=2)
+    w, V = np.linalg.eigh(H.dense())
+    sel = [40, 41, 42, 43, 60, 61]
+    g = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(g.normal(size=(6, 6)) + 1j * g.normal(size=(6, 6)))
+    rho, Vr, res = orc.harmonic_ritz(H, V[:, sel] @ Q, 0.17)
+    assert np.abs(rho - w[sel]).max() < 1e-12
+    assert res.max() < 1e-12
+
+
+def test_solve_ti_4x4x4_harmonic_vs_dense(orc):
+    """The scheme with harmonic Ritz extraction returns the dense spectrum's
+    window eigenvalues."""
+    H = orc.ti_hamiltonian(4, 4, 4, pbc=3, V=1.0, seed=1)
+    w = np.linalg.eigvalsh(H.dense())
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[3] + aw[4])
+    st, ev, res, V, stats = orc.chebfd_solve(H, -d, d, 16, 60, eps=1e-9, seed=3, harmonic=True)
+    want = w[np.abs(w) <= d]
+    assert st == 0 and ev.size == want.size == 4
+    a, b = stats["a"], stats["b"]
+    assert np.abs(ev - want).max() < 1e-10 * max(abs(a), abs(b))
+    assert np.linalg.norm(H.dense() @ V - V * ev, axis=0).max() <= 1e-9
