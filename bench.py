@@ -193,11 +193,13 @@ def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
     del H
     torch.cuda.empty_cache()
     out = {"workload": wname, "storage": storage,
-           "precision": "c128" if prec == B.PREC_C128 else "c64 sweep + c128 polish",
+           "precision": ("c128" if prec == B.PREC_C128
+                         else "c64 sweep + FP32 correction polish (FP64 accuracy)"),
            "bounds": [round(a, 4), round(b, 4), bounds], "window": [-d, d], "n_s": w["n_s"],
            "n_p": n_p, "time_to_solution_s": round(T, 3), "status": int(rc),
            "eigenpairs_found": int(ev.size), "max_residual": float(rs.max()) if rs.size else None,
            "iterations": stats["iterations"], "iterations_c64": stats["iterations_c64"],
+           "iterations_correction": stats["iterations_corr"],
            "n_mvm": stats["n_mvm"], "t_filter_s": round(stats["t_filter"], 3),
            "t_ortho_s": round(stats["t_ortho"], 3), "t_rr_s": round(stats["t_rr"], 3)}
     if prec != B.PREC_C128 and stats["sweep_evals"].size:

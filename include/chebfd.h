@@ -59,6 +59,12 @@ typedef struct chebfd_result chebfd_result;
 /* arithmetic of the filter sweep */
 #define CHEBFD_PREC_C128 0   /* complex128 storage, FP64 recurrence */
 #define CHEBFD_PREC_C64 1    /* complex64 storage, FP32 recurrence */
+/* history only: an FP32 correction pass of the precision form's polish */
+#define CHEBFD_PREC_C64_CORRECTION 2
+
+/* polish of the precision form (chebfd_params.polish) */
+#define CHEBFD_POLISH_CORRECTION 0   /* FP32 correction passes (default) */
+#define CHEBFD_POLISH_FP64 1         /* FP64 filter passes */
 
 /* matrix storage */
 #define CHEBFD_STORAGE_SELL 0     /* SELL-C-sigma, values and column indices */
@@ -140,6 +146,17 @@ int chebfd_matrix_destroy(chebfd_matrix *H);
 int chebfd_coeffs(double lam_lo, double lam_hi, double a, double b, int n_p, int kernel,
                   double mu, double *gamma_out);
 
+/* Division of the filter polynomial by a linear factor (host only): for
+ * p(y) = sum_{n=0}^{n_p} gamma_n T_n(y) in the scaled variable
+ * y = (2x - a - b) / (b - a) and t = (2 lambda - a - b) / (b - a), writes the
+ * n_p coefficients d_0 .. d_{n_p - 1} of q(y) = (p(y) - p(t)) / (y - t) to
+ * d_out and p(t) to *p_out (may be NULL).  Then for any vector v,
+ * p(H~) v = p(t) v + q(H~) (H~ - t) v, H~ = alpha H + beta -- the identity
+ * behind the precision form's correction passes.  Backward recurrence from
+ * the top coefficient (the intermediate values of Clenshaw's sum). */
+int chebfd_coeffs_divided(const double *gamma, int n_p, double a, double b, double lambda,
+                          double *d_out, double *p_out);
+
 /* Damping factor sigma and quality eta = -n_p / log10(sigma) of a filter
  * polynomial (Sec. 2.3): sigma = max |p| outside the search interval
  * [s_lo, s_hi] over [a, b] divided by min |p| inside [t_lo, t_hi]. */
@@ -174,6 +191,18 @@ int chebfd_optimal_np(double a, double b, double t_lo, double t_hi, double s_lo,
 int chebfd_filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
                         const double *gamma, int n_p, double a, double b, void *X, void *U,
                         void *W, int64_t n_s, int64_t ld, double *moments_dev);
+
+/* The filter with a coefficient sequence of its own for every column (the
+ * correction pass of the precision form, where column j carries the
+ * coefficients of (p(y) - p(t_j)) / (y - t_j) from chebfd_coeffs_divided):
+ *   X[:, j] <- sum_{n=0}^{n_p} gcol[n * ldg + j] T_n(alpha H + beta) X[:, j].
+ * gcol: DEVICE array of n_p + 1 rows of ldg >= n_s doubles (read only).
+ * complex64 only (UNSUPPORTED otherwise); no moments.  Buffers, layout and
+ * errors as chebfd_filter_apply (the coefficients are not checked for
+ * finiteness: they are on the device). */
+int chebfd_filter_apply_columns(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                                const double *gcol, int64_t ldg, int n_p, double a, double b,
+                                void *X, void *U, void *W, int64_t n_s, int64_t ld);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -481,6 +510,20 @@ typedef struct {
                                 orthonormal basis with the Ritz pairs of H
                                 inside it.  One more Gram (of H X) per
                                 iteration.  0 (default): Ritz pairs. */
+    int polish;              /* C64 only, after the sweep:
+                                CHEBFD_POLISH_CORRECTION (default) filters in
+                                FP32 with FP64 accuracy: for a Ritz pair
+                                (theta, v), with y = alpha x + beta and
+                                t = alpha theta + beta, p(y) = p(t) + (y - t)
+                                q_t(y) gives p(H~) v = p(t) v + q_t(H~) r,
+                                r = (H~ - t) v (formed in FP64), and only
+                                q_t(H~) r -- of the size of the residual --
+                                is filtered in complex64, column j with the
+                                coefficients of its own q_t
+                                (chebfd_coeffs_divided); a pass that stops
+                                reducing the residuals hands over to FP64
+                                passes.  CHEBFD_POLISH_FP64: FP64 filter
+                                passes throughout the polish. */
 } chebfd_params;
 
 typedef struct {
@@ -496,6 +539,7 @@ typedef struct {
     int n_p_used;            /* filter degree of the last iteration */
     double n_t_estimate;     /* adapt = 1: KPM count of the window (Eq.
                                 DOS:target) from the first pass; else 0 */
+    int iterations_corr;     /* FP32 correction passes of the polish */
 } chebfd_stats;
 
 /* Fills `p` with defaults: Lanczos kernel mu = 2, eps 1e-9, max_iter 50, C128,
@@ -532,7 +576,9 @@ int chebfd_result_destroy(chebfd_result *r);
  * restart on the Gershgorin interval the history is the restarted run's. */
 typedef struct {
     int64_t n_mvm;
-    int precision;
+    int precision;           /* CHEBFD_PREC_C128 (FP64 pass), C64 (FP32
+                                sweep) or C64_CORRECTION (FP32 correction
+                                pass of the polish) */
     int n_locked;
     int n_converged;
     int n_accepted;

@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchebfd.so")
 
 PREC_C128, PREC_C64 = 0, 1
+PREC_C64_CORRECTION = 2          # history only: an FP32 correction pass
+POLISH_CORRECTION, POLISH_FP64 = 0, 1
 STORAGE_SELL, STORAGE_STENCIL = 0, 1
 KERNELS = {"none": 0, "fejer": 1, "jackson": 2, "lanczos": 3}
 OK, NOT_CONVERGED, SEARCH_SPACE_TOO_SMALL = 0, 1, 2
@@ -34,7 +36,7 @@ class Params(C.Structure):
                 ("a", C.c_double), ("b", C.c_double), ("seed", C.c_uint64),
                 ("gamma_corr", C.c_void_p), ("polish_switch", C.c_double), ("vectors", C.c_int),
                 ("verbose", C.c_int), ("bounds", C.c_int), ("adapt", C.c_int),
-                ("harmonic", C.c_int)]
+                ("harmonic", C.c_int), ("polish", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -42,7 +44,8 @@ class Stats(C.Structure):
                 ("n_locked", C.c_int), ("refilled", C.c_int), ("n_mvm", C.c_int64),
                 ("a", C.c_double), ("b", C.c_double), ("t_total", C.c_double),
                 ("t_filter", C.c_double), ("t_ortho", C.c_double), ("t_rr", C.c_double),
-                ("max_residual", C.c_double), ("n_p_used", C.c_int), ("n_t_estimate", C.c_double)]
+                ("max_residual", C.c_double), ("n_p_used", C.c_int), ("n_t_estimate", C.c_double),
+                ("iterations_corr", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -83,11 +86,14 @@ def lib():
         "chebfd_matrix_info": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "chebfd_matrix_destroy": (i32, [vp]),
         "chebfd_coeffs": (i32, [dbl, dbl, dbl, dbl, i32, i32, dbl, vp]),
+        "chebfd_coeffs_divided": (i32, [vp, i32, dbl, dbl, dbl, vp, vp]),
         "chebfd_filter_quality": (i32, [vp, i32, dbl, dbl, dbl, dbl, dbl, dbl, vp, vp]),
         "chebfd_optimal_np": (i32, [dbl, dbl, dbl, dbl, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "chebfd_filter_apply": (i32, [vp, vp, i32, vp, i32, dbl, dbl, vp, vp, vp, i64, i64, vp]),
         "chebfd_filter_apply_noalloc": (i32, [vp, vp, i32, vp, i32, dbl, dbl, vp, vp, vp, i64,
                                               i64, vp]),
+        "chebfd_filter_apply_columns": (i32, [vp, vp, i32, vp, i64, i32, dbl, dbl, vp, vp, vp,
+                                              i64, i64]),
         "chebfd_lanczos_bounds": (i32, [vp, vp, i32, u64, dbl, vp, vp]),
         "chebfd_spmm": (i32, [vp, vp, i32, vp, vp, i64, i64, dbl, dbl]),
         "chebfd_gram": (i32, [vp, i32, vp, i64, i64, vp, i64, i64, i64, vp]),
@@ -139,7 +145,8 @@ def exported_symbols():
                         "chebfd_last_error chebfd_version chebfd_matrix_from_csr chebfd_matrix_ti "
                         "chebfd_matrix_info chebfd_matrix_destroy chebfd_coeffs "
                         "chebfd_filter_quality chebfd_optimal_np chebfd_filter_apply "
-                        "chebfd_filter_apply_noalloc chebfd_spmm "
+                        "chebfd_filter_apply_noalloc chebfd_filter_apply_columns "
+                        "chebfd_coeffs_divided chebfd_spmm "
                         "chebfd_lanczos_bounds "
                         "chebfd_gram chebfd_block_times chebfd_residual_norms "
                         "chebfd_random_block chebfd_convert chebfd_kpm_moments chebfd_host_eigh "
@@ -177,6 +184,15 @@ def _dbl(a):
 # ---------------------------------------------------------------------------
 # host-only functions
 # ---------------------------------------------------------------------------
+def chebfd_coeffs_divided(gamma, a, b, lam):
+    """(d, p(t)): coefficients of (p(y) - p(t)) / (y - t), t the scaled lam."""
+    g = _dbl(gamma)
+    d = np.empty(g.size - 1)
+    pt = C.c_double()
+    _check(lib().chebfd_coeffs_divided(_ptr(g), g.size - 1, a, b, lam, _ptr(d), C.byref(pt)))
+    return d, pt.value
+
+
 def chebfd_coeffs(lam_lo, lam_hi, a, b, n_p, kernel="lanczos", mu=2.0):
     out = np.empty(n_p + 1)
     k = KERNELS[kernel] if isinstance(kernel, str) else kernel
@@ -312,6 +328,17 @@ def chebfd_filter_apply_noalloc(ctx, H, gamma, a, b, X, U, W, moments=None, n_s=
     _check(lib().chebfd_filter_apply_noalloc(ctx.h, H.h, _prec(X), _ptr(g), g.size - 1, a, b,
                                              _ptr(X), _ptr(U), _ptr(W), n_s, _ld(X),
                                              _ptr(moments)))
+
+
+def chebfd_filter_apply_columns(ctx, H, gcol, a, b, X, U, W, n_s=None):
+    """Per-column coefficients: gcol is a device float64 tensor of shape
+    (n_p + 1, ldg >= n_s)."""
+    n_s = X.shape[1] if n_s is None else n_s
+    if gcol.dim() != 2 or gcol.stride(1) != 1 or gcol.dtype.itemsize != 8:
+        raise ValueError("gcol must be a 2-D float64 tensor with unit column stride")
+    _check(lib().chebfd_filter_apply_columns(ctx.h, H.h, _prec(X), _ptr(gcol), gcol.stride(0),
+                                             gcol.shape[0] - 1, a, b, _ptr(X), _ptr(U), _ptr(W),
+                                             n_s, _ld(X)))
 
 
 def chebfd_spmm(ctx, H, X, Y, s_h=1.0, s_u=0.0):

@@ -120,7 +120,7 @@ int check_filter_args(const char *who, chebfd_ctx *ctx, const chebfd_matrix *H, 
 // The polynomial filter (Fig. fig:ChebFD) on caller buffers.
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom, int progress, double *partials)
+                 double *mom, int progress, double *partials, const double *gcol, int64_t ldg)
 {
     const double alpha = 2.0 / (b - a), beta = (a + b) / (a - b);
     double *part = partials;
@@ -156,9 +156,14 @@ int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double
     s.y = X;
     s.s_h = 2.0 * alpha;
     s.s_u = 2.0 * beta;
-    s.g0 = gamma[0];
-    s.g1 = gamma[1];
-    s.g2 = gamma[2];
+    if (gcol) {
+        s.gcol = gcol;
+        s.ldg = ldg;
+    } else {
+        s.g0 = gamma[0];
+        s.g1 = gamma[1];
+        s.g2 = gamma[2];
+    }
     if ((rc = launch_step(ctx, H, s, &n_part))) return rc;
     if (mom && (rc = launch_moment_finalize(ctx, part, n_part, n_s, MODE_SECOND, 2, mom))) return rc;
     void *u = U, *w = W;
@@ -169,7 +174,8 @@ int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double
         s.wold = w;
         s.wout = w;
         s.y = X;
-        s.g0 = gamma[k];
+        if (gcol) s.gcol = gcol + (int64_t)k * ldg;
+        else s.g0 = gamma[k];
         if ((rc = launch_step(ctx, H, s, &n_part))) return rc;
         if (mom && (rc = launch_moment_finalize(ctx, part, n_part, n_s, MODE_STEP, k, mom)))
             return rc;
@@ -257,6 +263,30 @@ int chebfd_filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
     if (rc) return rc;
     CHEBFD_HIP(hipSetDevice(ctx->device));
     return filter_apply(ctx, H, precision, gamma, n_p, a, b, X, U, W, n_s, ld, moments_dev);
+}
+
+int chebfd_filter_apply_columns(chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
+                                const double *gcol, int64_t ldg, int n_p, double a, double b,
+                                void *X, void *U, void *W, int64_t n_s, int64_t ld)
+{
+    static const char *who = "chebfd_filter_apply_columns";
+    if (!ctx || !H || !gcol) return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": NULL argument");
+    if (precision != CHEBFD_PREC_C64)
+        return fail(CHEBFD_ERR_UNSUPPORTED, std::string(who) + ": complex64 only");
+    if (n_p < 2) return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": n_p must be >= 2");
+    if (ldg < n_s) return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": ldg < n_s");
+    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b))
+        return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": need finite a < b");
+    int rc;
+    if ((rc = check_block(who, precision, X, H->n, n_s, ld, true)) ||
+        (rc = check_block(who, precision, U, H->n, n_s, ld, true)) ||
+        (rc = check_block(who, precision, W, H->n, n_s, ld, true)))
+        return rc;
+    if (X == U || X == W || U == W)
+        return fail(CHEBFD_ERR_INVALID_ARG, std::string(who) + ": X, U, W must be distinct");
+    CHEBFD_HIP(hipSetDevice(ctx->device));
+    return filter_apply(ctx, H, precision, nullptr, n_p, a, b, X, U, W, n_s, ld, nullptr, 0,
+                        nullptr, gcol, ldg);
 }
 
 int chebfd_spmm(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, const void *X, void *Y,

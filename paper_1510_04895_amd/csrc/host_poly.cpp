@@ -66,6 +66,28 @@ double poly_value(const double *gamma, int n_p, double a, double b, double x)
     return gamma[0] + y * b1 - b2;
 }
 
+// Division by a linear factor in the Chebyshev basis.  For
+// p(y) = sum_{n=0}^{N} c_n T_n(y) and a point t, q(y) = (p(y) - p(t)) / (y - t)
+// = sum_{n=0}^{N-1} d_n T_n(y).  With y T_0 = T_1 and 2 y T_n = T_{n+1} +
+// T_{n-1} (n >= 1), matching the T_m terms of (y - t) q = p - p(t) gives
+// from the top d_{m-1} = 2 c_m + 2 t d_m - d_{m+1} (m = N .. 2, d_N = d_{N+1}
+// = 0), then d_0 = c_1 + t d_1 - d_2 / 2, and the T_0 term leaves
+// p(t) = c_0 + t d_0 - d_1 / 2 (Clenshaw's sum: d_{m-1} / 2 and d_0 are its
+// intermediate values).  Writes d[0 .. N-1]; returns p(t).
+double cheb_divide(const double *c, int N, double t, double *d)
+{
+    double d1 = 0.0, d2 = 0.0;   // d_m, d_{m+1}
+    for (int m = N; m >= 2; --m) {
+        const double v = 2.0 * c[m] + 2.0 * t * d1 - d2;
+        d[m - 1] = v;
+        d2 = d1;
+        d1 = v;
+    }
+    const double d0 = c[1] + t * d1 - 0.5 * d2;
+    d[0] = d0;
+    return c[0] + t * d0 - 0.5 * d1;
+}
+
 // In-place iterative radix-2 complex FFT (length a power of two).
 void fft(std::vector<std::complex<double>> &v)
 {
@@ -142,6 +164,17 @@ extern "C" int chebfd_coeffs(double lam_lo, double lam_hi, double a, double b, i
     window_coeffs(lam_lo, lam_hi, a, b, n_p, gamma_out);
     damping(kernel, n_p, mu, g.data());
     for (int n = 0; n <= n_p; ++n) gamma_out[n] *= g[n];
+    return CHEBFD_OK;
+}
+
+extern "C" int chebfd_coeffs_divided(const double *gamma, int n_p, double a, double b,
+                                     double lambda, double *d_out, double *p_out)
+{
+    if (!gamma || !d_out || n_p < 2 || !(a < b) || !std::isfinite(lambda))
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_coeffs_divided: invalid arguments");
+    const double t = (2.0 * lambda - a - b) / (b - a);
+    const double pt = cheb_divide(gamma, n_p, t, d_out);
+    if (p_out) *p_out = pt;
     return CHEBFD_OK;
 }
 

@@ -126,6 +126,11 @@ struct StepArgs {
     double s_h, s_u;   // w = s_h H u + s_u u (- wold)
     double g0, g1, g2; // MODE_SECOND: y = g0 x + g1 u + g2 w; MODE_STEP: y += g0 w
     double *partials;  // moment partial sums, or nullptr
+    // per-column coefficients in place of g0..g2, or nullptr: row r of the
+    // device table at gcol + r * ldg holds one coefficient per column
+    // (MODE_SECOND reads rows 0..2, MODE_STEP row 0)
+    const double *gcol;
+    int64_t ldg;
 };
 
 // Launches one fused step; returns number of partial-sum rows written
@@ -150,6 +155,13 @@ int launch_random(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s, in
                   int64_t k0, int64_t m, uint64_t seed, uint64_t stream, uint64_t offset);
 int launch_convert(chebfd_ctx *ctx, int prec_in, const void *X, int prec_out, void *Y,
                    int64_t n, int64_t n_s, int64_t ld_in, int64_t ld_out);
+// Correction pass of the precision form: R = f32(HV - V diag(t)) with zero
+// columns k .. kk-1 (V, HV complex128, ld_v; R complex64, ld_r), and
+// V = V diag(p) + f64(D) (D complex64, ld_d).
+int launch_defect(chebfd_ctx *ctx, const void *V, const void *HV, const double *t_dev, void *R,
+                  int64_t n, int64_t k, int64_t kk, int64_t ld_v, int64_t ld_r);
+int launch_combine(chebfd_ctx *ctx, void *V, const void *D, const double *p_dev, int64_t n,
+                   int64_t k, int64_t ld_v, int64_t ld_d);
 int launch_phase_block(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s,
                        int64_t ld, uint64_t seed, uint64_t stream);
 int launch_bandwidth_probe(chebfd_ctx *ctx, void *buf, int64_t bytes, int reps, double *gbs);
@@ -159,9 +171,12 @@ int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, 
 // The filter of Fig. fig:ChebFD; with mom != nullptr the moment partial sums
 // go to `partials` (moment_partial_bytes long) or, if that is nullptr, to the
 // context's grow-only scratch.
+// With gcol != nullptr column j is filtered with its own coefficients
+// gcol[n * ldg + j], n = 0..n_p (a device table), and gamma is not read.
 int filter_apply(chebfd_ctx *ctx, const chebfd_matrix *H, int prec, const double *gamma, int n_p,
                  double a, double b, void *X, void *U, void *W, int64_t n_s, int64_t ld,
-                 double *mom, int progress = 0, double *partials = nullptr);
+                 double *mom, int progress = 0, double *partials = nullptr,
+                 const double *gcol = nullptr, int64_t ldg = 0);
 size_t moment_partial_bytes(const chebfd_ctx *ctx, const chebfd_matrix *H, int prec, int64_t n_s);
 int check_filter_args(const char *who, chebfd_ctx *ctx, const chebfd_matrix *H, int precision,
                       const double *gamma, int n_p, double a, double b, void *X, void *U,
@@ -180,6 +195,9 @@ int lanczos_bounds(chebfd_ctx *ctx, const chebfd_matrix *H, int k, uint64_t seed
 void window_coeffs(double lo, double hi, double a, double b, int n_p, double *c);
 void damping(int kernel, int n_p, double mu, double *g);
 double poly_value(const double *gamma, int n_p, double a, double b, double x);
+// coefficients d[0 .. N-1] of (p(y) - p(t)) / (y - t) for p = sum c_n T_n
+// (degree N, scaled variable); returns p(t)
+double cheb_divide(const double *c, int N, double t, double *d);
 void quality(const double *gamma, int n_p, double a, double b, double t_lo, double t_hi,
              double s_lo, double s_hi, double *sigma, double *eta);
 int herm_eig(int n, std::vector<double> &A /* 2*n*n, overwritten by vectors */,

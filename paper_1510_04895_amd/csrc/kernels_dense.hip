@@ -298,6 +298,40 @@ __global__ void k_convert(const TI *__restrict__ X, TO *__restrict__ Y, int64_t 
 
 inline unsigned nblocks(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
 
+// Scaled residual block of the correction pass, rounded to complex64:
+// R[:, j] = HV[:, j] - t_j V[:, j] for j < k (HV the scaled product
+// (alpha H + beta) V, t_j the scaled Ritz value), zero for k <= j < kk.
+__global__ void k_defect(const double *__restrict__ V, const double *__restrict__ HV,
+                         const double *__restrict__ t, float *__restrict__ R, int64_t n,
+                         int64_t k, int64_t kk, int64_t ld_v, int64_t ld_r)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * kk) return;
+    const int64_t i = idx / kk, j = idx - (idx / kk) * kk;
+    float re = 0.0f, im = 0.0f;
+    if (j < k) {
+        const double *v = V + 2 * (i * ld_v + j), *h = HV + 2 * (i * ld_v + j);
+        re = (float)__builtin_fma(-t[j], v[0], h[0]);
+        im = (float)__builtin_fma(-t[j], v[1], h[1]);
+    }
+    R[2 * (i * ld_r + j)] = re;
+    R[2 * (i * ld_r + j) + 1] = im;
+}
+
+// V[:, j] = p_j V[:, j] + D[:, j] (D complex64), j < k.
+__global__ void k_combine(double *__restrict__ V, const float *__restrict__ D,
+                          const double *__restrict__ pt, int64_t n, int64_t k, int64_t ld_v,
+                          int64_t ld_d)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * k) return;
+    const int64_t i = idx / k, j = idx - (idx / k) * k;
+    double *v = V + 2 * (i * ld_v + j);
+    const float *d = D + 2 * (i * ld_d + j);
+    v[0] = __builtin_fma(pt[j], v[0], (double)d[0]);
+    v[1] = __builtin_fma(pt[j], v[1], (double)d[1]);
+}
+
 // Attainable-bandwidth probes (the read-only reduction of Sec. 4.1, a copy,
 // and the fused step's five streams without the gather).  A workgroup owns
 // one contiguous tile of 256 x PU 16-byte elements and issues all PU
@@ -570,6 +604,27 @@ int launch_phase_block(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_
     else
         hipLaunchKernelGGL(k_phase<float>, dim3(nblocks(n * n_s, 256)), dim3(256), 0,
                            ctx->stream, (float *)X, n, n_s, ld, key);
+    CHEBFD_CHECK_LAUNCH();
+    return CHEBFD_OK;
+}
+
+int launch_defect(chebfd_ctx *ctx, const void *V, const void *HV, const double *t_dev, void *R,
+                  int64_t n, int64_t k, int64_t kk, int64_t ld_v, int64_t ld_r)
+{
+    if (n * kk == 0) return CHEBFD_OK;
+    hipLaunchKernelGGL(k_defect, dim3(nblocks(n * kk, 256)), dim3(256), 0, ctx->stream,
+                       (const double *)V, (const double *)HV, t_dev, (float *)R, n, k, kk, ld_v,
+                       ld_r);
+    CHEBFD_CHECK_LAUNCH();
+    return CHEBFD_OK;
+}
+
+int launch_combine(chebfd_ctx *ctx, void *V, const void *D, const double *p_dev, int64_t n,
+                   int64_t k, int64_t ld_v, int64_t ld_d)
+{
+    if (n * k == 0) return CHEBFD_OK;
+    hipLaunchKernelGGL(k_combine, dim3(nblocks(n * k, 256)), dim3(256), 0, ctx->stream,
+                       (double *)V, (const float *)D, p_dev, n, k, ld_v, ld_d);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }

@@ -70,12 +70,13 @@ __device__ __forceinline__ void add_hop(Pack<T, NB> (&acc)[4], const Site<T, NB>
     }
 }
 
-template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT, bool PC>
 __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc, T th, T mm,
                                                  const T *__restrict__ pot, int64_t nsites,
                                                  int64_t nblk, const T *__restrict__ u,
                                                  const T *wold, T *wout, T *y, int64_t n_s,
                                                  int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
+                                                 const double *__restrict__ gcol, int64_t ldg,
                                                  double *__restrict__ partials, int order,
                                                  int64_t nslab, int lg_xg, int tile)
 {
@@ -187,6 +188,8 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
             add_hop<T, NB, 2>(acc, un[4], tw[4], T(1));
             add_hop<T, NB, 2>(acc, un[5], tw[5], T(-1));
         }
+        T k0[NB], k1[NB], k2[NB];
+        lane_coeffs<T, NB, MODE == MODE_SECOND, PC>(gcol, ldg, c0, cnt, g0, g1, g2, k0, k1, k2);
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const int64_t off = 2 * ((4 * site + o) * ld + c0);
@@ -215,8 +218,8 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                 for (int e = 0; e < NB; ++e) {
                     w.re[e] -= xo.re[e];
                     w.im[e] -= xo.im[e];
-                    xn.re[e] = g0 * xo.re[e] + g1 * uo.o[o].re[e] + g2 * w.re[e];
-                    xn.im[e] = g0 * xo.im[e] + g1 * uo.o[o].im[e] + g2 * w.im[e];
+                    xn.re[e] = k0[e] * xo.re[e] + k1[e] * uo.o[o].re[e] + k2[e] * w.re[e];
+                    xn.im[e] = k0[e] * xo.im[e] + k1[e] * uo.o[o].im[e] + k2[e] * w.im[e];
                 }
                 store_pack_n<T, NB, NT>(wout + off, w, cnt);
                 store_pack_n<T, NB, NT>(y + off, xn, cnt);
@@ -233,8 +236,8 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
                 for (int e = 0; e < NB; ++e) {
                     w.re[e] -= wo.o[o].re[e];
                     w.im[e] -= wo.o[o].im[e];
-                    yv.re[e] += g0 * w.re[e];
-                    yv.im[e] += g0 * w.im[e];
+                    yv.re[e] += k0[e] * w.re[e];
+                    yv.im[e] += k0[e] * w.im[e];
                 }
                 store_pack_n<T, NB, NT>(wout + off, w, cnt);
                 store_pack_n<T, NB, NT>(y + off, yv, cnt);
@@ -295,7 +298,7 @@ int auto_order(const Stencil &S, int64_t n_s)
     return tiled_order_pays(S.L, (int64_t)(n_s < SW ? n_s : SW) * 2 * sizeof(T)) ? 1 : 0;
 }
 
-template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT>
+template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT, bool PC = false>
 int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
 {
     constexpr int SPB = 4 * (64 / LPS);
@@ -318,12 +321,12 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     int lg_xg = ilog2(ctx->tune_xcd_group);
     if (order == 1 && !ctx->tune_xcd_group) lg_xg = ilog2_64(bpr * S.L[1]);
     const T *pot = std::is_same<T, double>::value ? (const T *)S.pot64 : (const T *)S.pot32;
-    hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT>), dim3((unsigned)(nblk * nslab)),
+    hipLaunchKernelGGL((k_step_ti<T, LPS, NB, MODE, MOM, NT, PC>), dim3((unsigned)(nblk * nslab)),
                        dim3(256), 0, ctx->stream, S.L[0], S.L[1], S.L[2], S.pbc,
                        (T)(-0.5 * S.t), (T)S.m, pot, nsites, nblk, (const T *)a.u,
                        (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld, (T)a.s_h,
-                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, order, nslab, lg_xg,
-                       tile);
+                       (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.gcol, a.ldg, a.partials, order,
+                       nslab, lg_xg, tile);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }
@@ -332,6 +335,17 @@ template <typename T, int LPS, int NB, bool NT>
 int launch_ti_mode(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
 {
     const bool mom = a.partials != nullptr;
+    if (a.gcol && a.mode != MODE_APPLY) {
+        // per-column coefficients (complex64, no moments)
+        if constexpr (std::is_same<T, float>::value) {
+            if (mom) return fail(CHEBFD_ERR_UNSUPPORTED, "per-column coefficients: no moments");
+            return a.mode == MODE_SECOND
+                       ? launch_ti_t<T, LPS, NB, MODE_SECOND, false, NT, true>(ctx, S, a, n_part)
+                       : launch_ti_t<T, LPS, NB, MODE_STEP, false, NT, true>(ctx, S, a, n_part);
+        } else {
+            return fail(CHEBFD_ERR_UNSUPPORTED, "per-column coefficients: complex64 only");
+        }
+    }
     switch (a.mode) {
     case MODE_APPLY:
         return mom ? launch_ti_t<T, LPS, NB, MODE_APPLY, true, NT>(ctx, S, a, n_part)

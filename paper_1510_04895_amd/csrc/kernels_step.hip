@@ -248,7 +248,8 @@ template <typename T, int NB, int MODE, bool MOM, bool NT>
 __device__ __forceinline__ void finish_row(int64_t off, int cnt, const T (&ar)[NB],
                                            const T (&ai)[NB], const Pack<T, NB> &uo,
                                            const Pack<T, NB> &wo, Pack<T, NB> yv, T *wout, T *y,
-                                           T s_h, T s_u, T g0, T g1, T g2, double (&m0)[NB],
+                                           T s_h, T s_u, const T (&g0)[NB], const T (&g1)[NB],
+                                           const T (&g2)[NB], double (&m0)[NB],
                                            double (&m1)[NB], double (&m2)[NB])
 {
     // explicit fused multiply-adds throughout, so that every kernel that
@@ -278,8 +279,8 @@ __device__ __forceinline__ void finish_row(int64_t off, int cnt, const T (&ar)[N
         for (int e = 0; e < NB; ++e) {
             w.re[e] -= wo.re[e];
             w.im[e] -= wo.im[e];
-            xn.re[e] = fmadd<T>(g2, w.re[e], fmadd<T>(g1, uo.re[e], g0 * wo.re[e]));
-            xn.im[e] = fmadd<T>(g2, w.im[e], fmadd<T>(g1, uo.im[e], g0 * wo.im[e]));
+            xn.re[e] = fmadd<T>(g2[e], w.re[e], fmadd<T>(g1[e], uo.re[e], g0[e] * wo.re[e]));
+            xn.im[e] = fmadd<T>(g2[e], w.im[e], fmadd<T>(g1[e], uo.im[e], g0[e] * wo.im[e]));
         }
         store_pack_n<T, NB, NT>(wout + off, w, cnt);
         store_pack_n<T, NB, NT>(y + off, xn, cnt);
@@ -288,8 +289,8 @@ __device__ __forceinline__ void finish_row(int64_t off, int cnt, const T (&ar)[N
         for (int e = 0; e < NB; ++e) {
             w.re[e] -= wo.re[e];
             w.im[e] -= wo.im[e];
-            yv.re[e] = fmadd<T>(g0, w.re[e], yv.re[e]);
-            yv.im[e] = fmadd<T>(g0, w.im[e], yv.im[e]);
+            yv.re[e] = fmadd<T>(g0[e], w.re[e], yv.re[e]);
+            yv.im[e] = fmadd<T>(g0[e], w.im[e], yv.im[e]);
         }
         store_pack_n<T, NB, NT>(wout + off, w, cnt);
         store_pack_n<T, NB, NT>(y + off, yv, cnt);
@@ -305,14 +306,15 @@ __device__ __forceinline__ void finish_row(int64_t off, int cnt, const T (&ar)[N
 
 // The fused step on one row and one pack of columns (modes as above), with
 // the moment dot products accumulated in m0..m2.
-template <typename T, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, int RPP>
+template <typename T, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, int RPP, bool PC>
 __device__ __forceinline__ void step_row(int row, int64_t c0, int cnt, int len,
                                          const int32_t *scol, const T *sval,
                                          const int32_t *__restrict__ col,
                                          const T *__restrict__ val, int64_t e0, int C,
                                          const T *__restrict__ u, const T *wold, T *wout, T *y,
                                          int64_t ld, T s_h, T s_u, T g0, T g1, T g2,
-                                         double (&m0)[NB], double (&m1)[NB], double (&m2)[NB])
+                                         const double *gcol, int64_t ldg, double (&m0)[NB],
+                                         double (&m1)[NB], double (&m2)[NB])
 {
     const uint32_t row_bytes = (uint32_t)(ld * 2 * sizeof(T));
     const char *ub = reinterpret_cast<const char *>(u + 2 * c0);
@@ -327,7 +329,9 @@ __device__ __forceinline__ void step_row(int row, int64_t c0, int cnt, int len,
         row_product_staged<T, NB, GB, RPP>(ub, row_bytes, cnt, len, scol, sval, ar, ai);
     else
         row_product_stream<T, NB, GB>(ub, row_bytes, cnt, len, col, val, e0, C, ar, ai);
-    finish_row<T, NB, MODE, MOM, NT>(off, cnt, ar, ai, uo, wo, yv, wout, y, s_h, s_u, g0, g1, g2,
+    T k0[NB], k1[NB], k2[NB];
+    lane_coeffs<T, NB, MODE == MODE_SECOND, PC>(gcol, ldg, c0, cnt, g0, g1, g2, k0, k1, k2);
+    finish_row<T, NB, MODE, MOM, NT>(off, cnt, ar, ai, uo, wo, yv, wout, y, s_h, s_u, k0, k1, k2,
                                      m0, m1, m2);
 }
 
@@ -368,13 +372,14 @@ __device__ __forceinline__ void moment_partials(double (&m0)[NB], double (&m1)[N
 
 // One row block per workgroup; rows longer than the LDS stage read the
 // index stream directly.
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, bool PC>
 __global__ __launch_bounds__(256) void k_step_sell(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
     const T *__restrict__ val, int C, int RB, int lg_bpc, uint32_t nrb,
     const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
-    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg, int spw, int nslab)
+    T s_u, T g0, T g1, T g2, const double *__restrict__ gcol, int64_t ldg,
+    double *__restrict__ partials, int lg_xg, int spw, int nslab)
 {
     constexpr int RPW = 64 / LPR;        // rows per wave
     constexpr int RPP = 4 * RPW;         // rows per workgroup
@@ -410,9 +415,9 @@ __global__ __launch_bounds__(256) void k_step_sell(
 #pragma unroll
         for (int e = 0; e < NB; ++e) m0[e] = m1[e] = m2[e] = 0.0;
         if (c0 < n_s && row >= 0)
-            step_row<T, NB, MODE, MOM, NT, STAGED, GB, RPP>(
+            step_row<T, NB, MODE, MOM, NT, STAGED, GB, RPP, PC>(
                 row, c0, cnt, L.len, s_col + q, s_val + 2 * q, col, val, L.base + L.r0 + q, C,
-                u, wold, wout, y, ld, s_h, s_u, g0, g1, g2, m0, m1, m2);
+                u, wold, wout, y, ld, s_h, s_u, g0, g1, g2, gcol, ldg, m0, m1, m2);
         if (MOM)
             moment_partials<LPR, NB>(m0, m1, m2, red, wave, lane, L.rb, c0, cnt, n_s, partials);
     }
@@ -538,13 +543,14 @@ __device__ __forceinline__ void group_product_staged(const char *ub, uint32_t ro
 }
 
 // One block of RB <= QPW groups per workgroup (QPW = 4 * 64 / LPR groups).
-template <typename T, int LPR, int NB, int G, int MODE, bool MOM, bool NT, int GB>
+template <typename T, int LPR, int NB, int G, int MODE, bool MOM, bool NT, int GB, bool PC>
 __global__ __launch_bounds__(256) void k_step_sellg(
     const int64_t *__restrict__ chunk_ptr, const int32_t *__restrict__ chunk_len,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
     const T *__restrict__ val, int P, int RB, int lg_bpc, uint32_t nrb,
     const T *__restrict__ u, const T *wold, T *wout, T *y, int64_t n_s, int64_t ld, T s_h,
-    T s_u, T g0, T g1, T g2, double *__restrict__ partials, int lg_xg, int spw, int nslab)
+    T s_u, T g0, T g1, T g2, const double *__restrict__ gcol, int64_t ldg,
+    double *__restrict__ partials, int lg_xg, int spw, int nslab)
 {
     constexpr int QPV = 64 / LPR;        // groups per wave
     constexpr int QPW = 4 * QPV;         // groups per workgroup
@@ -594,11 +600,13 @@ __global__ __launch_bounds__(256) void k_step_sellg(
             T ar[G][NB], ai[G][NB];
             group_product_staged<T, NB, G, GB, QPW>(ub, row_bytes, cnt, L.len, s_col + q,
                                                     s_val + 2 * G * q, ar, ai);
+            T k0[NB], k1[NB], k2[NB];
+            lane_coeffs<T, NB, MODE == MODE_SECOND, PC>(gcol, ldg, c0, cnt, g0, g1, g2, k0, k1, k2);
 #pragma unroll
             for (int k = 0; k < G; ++k)
                 if (row[k] >= 0)
                     finish_row<T, NB, MODE, MOM, NT>(off[k], cnt, ar[k], ai[k], uo[k], wo[k],
-                                                     yv[k], wout, y, s_h, s_u, g0, g1, g2, m0,
+                                                     yv[k], wout, y, s_h, s_u, k0, k1, k2, m0,
                                                      m1, m2);
         }
         if (MOM)
@@ -693,40 +701,40 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
     return CHEBFD_OK;
 }
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool STAGED, int GB, bool PC>
 void launch_sell_k(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, const SellGeom &g)
 {
     const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB>),
+    hipLaunchKernelGGL((k_step_sell<T, LPR, NB, MODE, MOM, NT, STAGED, GB, PC>),
                        dim3(g.nrb * g.ngroups), dim3(256), 0, ctx->stream, S.chunk_ptr,
                        S.chunk_len, S.perm, S.col, val, S.C, g.RB, g.lg_bpc, g.nrb,
                        (const T *)a.u, (const T *)a.wold, (T *)a.wout, (T *)a.y, a.n_s, a.ld,
-                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.partials, g.lg_xg, g.spw,
-                       (int)g.nslab);
+                       (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2, a.gcol, a.ldg, a.partials,
+                       g.lg_xg, g.spw, (int)g.nslab);
 }
 
-template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT>
+template <typename T, int LPR, int NB, int MODE, bool MOM, bool NT, bool PC = false>
 int launch_sell_t(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
 {
     SellGeom g;
     if (int rc = sell_geom<LPR, NB>(ctx, S, a, g)) return rc;
     if (S.group > 1) {
         const T *val = std::is_same<T, double>::value ? (const T *)S.val64 : (const T *)S.val32;
-        const auto kern = S.group == 4 ? k_step_sellg<T, LPR, NB, 4, MODE, MOM, NT, 16>
-                                       : k_step_sellg<T, LPR, NB, 2, MODE, MOM, NT, 16>;
+        const auto kern = S.group == 4 ? k_step_sellg<T, LPR, NB, 4, MODE, MOM, NT, 16, PC>
+                                       : k_step_sellg<T, LPR, NB, 2, MODE, MOM, NT, 16, PC>;
         hipLaunchKernelGGL(kern, dim3(g.nrb * g.ngroups), dim3(256), 0, ctx->stream,
                            S.chunk_ptr, S.chunk_len, S.perm, S.col, val, S.C / S.group, g.RB,
                            g.lg_bpc, g.nrb, (const T *)a.u, (const T *)a.wold, (T *)a.wout,
                            (T *)a.y, a.n_s, a.ld, (T)a.s_h, (T)a.s_u, (T)a.g0, (T)a.g1, (T)a.g2,
-                           a.partials, g.lg_xg, g.spw, (int)g.nslab);
+                           a.gcol, a.ldg, a.partials, g.lg_xg, g.spw, (int)g.nslab);
         CHEBFD_CHECK_LAUNCH();
         return CHEBFD_OK;
     }
     // rows that fit the LDS stage -> staged variant, else the index stream
     if (S.max_len <= LS)
-        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16>(ctx, S, a, g);
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, true, 16, PC>(ctx, S, a, g);
     else
-        launch_sell_k<T, LPR, NB, MODE, MOM, NT, false, 8>(ctx, S, a, g);
+        launch_sell_k<T, LPR, NB, MODE, MOM, NT, false, 8, PC>(ctx, S, a, g);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
 }
@@ -735,6 +743,17 @@ template <typename T, int LPR, int NB, bool NT>
 int launch_sell_mode(chebfd_ctx *ctx, const Sell &S, const StepArgs &a)
 {
     const bool mom = a.partials != nullptr;
+    if (a.gcol && a.mode != MODE_APPLY) {
+        // per-column coefficients (complex64, no moments)
+        if constexpr (std::is_same<T, float>::value) {
+            if (mom) return fail(CHEBFD_ERR_UNSUPPORTED, "per-column coefficients: no moments");
+            return a.mode == MODE_SECOND
+                       ? launch_sell_t<T, LPR, NB, MODE_SECOND, false, NT, true>(ctx, S, a)
+                       : launch_sell_t<T, LPR, NB, MODE_STEP, false, NT, true>(ctx, S, a);
+        } else {
+            return fail(CHEBFD_ERR_UNSUPPORTED, "per-column coefficients: complex64 only");
+        }
+    }
     switch (a.mode) {
     case MODE_APPLY:
         return mom ? launch_sell_t<T, LPR, NB, MODE_APPLY, true, NT>(ctx, S, a)

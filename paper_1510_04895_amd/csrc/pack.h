@@ -88,4 +88,32 @@ __device__ __forceinline__ void store_pack_n(T *p, const Pack<T, NB> &v, int cnt
         }
 }
 
+// The filter coefficients of a lane's columns c0 .. c0 + cnt - 1: the
+// launch's scalars, or (PC) each column's own from the table gcol (row r at
+// gcol + r * ldg; rows 0..2 in the second step, row 0 in later ones).  PC
+// is a separate instantiation so that the plain step keeps its registers.
+template <typename T, int NB, bool SECOND, bool PC>
+__device__ __forceinline__ void lane_coeffs(const double *gcol, int64_t ldg, int64_t c0, int cnt,
+                                            T g0, T g1, T g2, T (&k0)[NB], T (&k1)[NB],
+                                            T (&k2)[NB])
+{
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+        k0[e] = g0;
+        k1[e] = g1;
+        k2[e] = g2;
+    }
+    if (PC) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e)
+            if (e < cnt) {
+                k0[e] = (T)gcol[c0 + e];
+                if (SECOND) {
+                    k1[e] = (T)gcol[ldg + c0 + e];
+                    k2[e] = (T)gcol[2 * ldg + c0 + e];
+                }
+            }
+    }
+}
+
 }  // namespace chebfd

@@ -469,6 +469,70 @@ struct Solver {
         return CHEBFD_OK;
     }
 
+    // Correction pass of the precision form's polish: FP32 arithmetic with
+    // FP64 accuracy.  With y = alpha x + beta, p(y) = p(t) + (y - t) q_t(y)
+    // for every t (q_t of degree n_p - 1), so for a Ritz pair (theta, v) and
+    // t = alpha theta + beta
+    //     p(H~) v = p(t) v + q_t(H~) r,   r = (H~ - t) v,
+    // exactly.  r is formed in FP64 and rounded to complex64, and only
+    // q_t(H~) r is filtered in FP32: its rounding error scales with |r|
+    // (the residual) instead of |v|, so a pass lowers the FP32 floor by
+    // about that ratio (iterative refinement of the filter).  Column j is
+    // filtered with the coefficients of its own q_t (cheb_divide), p(t) v is
+    // added back in FP64.  In: X = the k active Ritz vectors (complex128),
+    // th their Ritz values.  Out: X = p(H~) X; U, W the two other complex128
+    // blocks.  The complex64 filter buffers U32, W32 live in B[0], so X is
+    // moved out of B[0] first; the block that held H~ X carries the
+    // coefficient table during the filter.
+    int correction_pass(void *const B[3], void *&X, void *&U, void *&W, void *X32, void *U32,
+                        void *W32, int k, const std::vector<double> &th)
+    {
+        int rc;
+        const size_t bytes = (size_t)n * ns * 16;
+        if (X == B[0]) {
+            CHEBFD_HIP(hipMemcpyAsync(B[1], X, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+            X = B[1];
+        }
+        void *O = X == B[1] ? B[2] : B[1];
+        const double alpha = 2.0 / (b - a), beta = (a + b) / (a - b);
+        StepArgs s{};
+        s.mode = MODE_APPLY;
+        s.precision = CHEBFD_PREC_C128;
+        s.u = X;
+        s.wout = O;
+        s.n = n;
+        s.n_s = k;
+        s.ld = ns;
+        s.s_h = alpha;
+        s.s_u = beta;
+        if ((rc = launch_step(ctx, H, s, nullptr))) return rc;   // O = H~ X
+        // per column: t_j, p(t_j) and the coefficients of q_{t_j}; the
+        // filter runs degree max(2, n_p - 1) (zero padding) over kk columns
+        // (even for complex64 packs; the padding column is zero)
+        const int kk = k & 1 ? k + 1 : k;
+        const int deg = std::max(2, p.n_p - 1);
+        std::vector<double> t(k), pt(k), d(p.n_p), tab((size_t)(deg + 1) * kk, 0.0);
+        for (int j = 0; j < k; ++j) {
+            t[j] = std::min(1.0, std::max(-1.0, alpha * th[j] + beta));
+            pt[j] = cheb_divide(gamma.data(), p.n_p, t[j], d.data());
+            for (int m = 0; m < p.n_p; ++m) tab[(size_t)m * kk + j] = d[m];
+        }
+        if ((rc = up(dTheta, t.data(), (size_t)k * 8))) return rc;
+        if ((rc = launch_defect(ctx, X, O, dTheta, X32, n, k, kk, ns, ns))) return rc;
+        // the table replaces H~ X in O (stream order: after the defect kernel)
+        if ((rc = up(O, tab.data(), tab.size() * 8))) return rc;
+        if ((rc = up(dRes, pt.data(), (size_t)k * 8))) return rc;
+        if ((rc = sync())) return rc;   // the host vectors go out of scope
+        if ((rc = filter_apply(ctx, H, CHEBFD_PREC_C64, nullptr, deg, a, b, X32, U32, W32, kk, ns,
+                               nullptr, p.verbose ? 1024 : 0, nullptr, (const double *)O, kk)))
+            return rc;
+        if ((rc = launch_combine(ctx, X, X32, dRes, n, k, ns, ns))) return rc;
+        st.n_mvm += (int64_t)k * (deg + 1);
+        U = O;
+        W = B[0];
+        return CHEBFD_OK;
+    }
+
     int run(chebfd_result *out)
     {
         const auto t0 = clk::now();
@@ -508,6 +572,12 @@ struct Solver {
         std::vector<double> theta, res, S, w;
         int last_active = ns;
         int ns_act = ns;   // search-space size (the FP64 polish may narrow it)
+        // polish by FP32 correction passes: Ritz values of the active
+        // columns, and the largest accepted residual of the last pass
+        bool corr = false;
+        std::vector<double> th_act;
+        double corr_worst = INFINITY;
+        int corr_conv = -1;
         std::vector<int> keep_idx, conv_idx;
         const double seps = std::sqrt(p.eps);
         int it;
@@ -519,7 +589,10 @@ struct Solver {
             auto ta = clk::now();
             // the first pass of an adaptive solve also returns the moments
             double *mom = (p.adapt && it == 1) ? (double *)(base + L.off_mom) : nullptr;
-            if (prec == CHEBFD_PREC_C64) {
+            if (corr) {
+                rc = correction_pass(B, X, U, W, X32, U32, W32, k, th_act);
+                ++st.iterations_corr;
+            } else if (prec == CHEBFD_PREC_C64) {
                 rc = filter_apply(ctx, H, CHEBFD_PREC_C64, gamma.data(), p.n_p, a, b, X32, U32,
                                   W32, k & 1 ? k + 1 : k, ns, mom, p.verbose ? 1024 : 0);
                 ++st.iterations_c64;
@@ -528,7 +601,7 @@ struct Solver {
                                   ns, mom, p.verbose ? 1024 : 0);
             }
             if (rc) return rc;
-            st.n_mvm += (int64_t)k * p.n_p;
+            if (!corr) st.n_mvm += (int64_t)k * p.n_p;
             if ((rc = sync())) return rc;
             if (mom && (rc = reselect_degree(mom, k & 1 && prec == CHEBFD_PREC_C64 ? k + 1 : k,
                                              k)))
@@ -621,7 +694,7 @@ struct Solver {
                 // of this iteration (and of the pairs locked before it)
                 chebfd_iter_info h{};
                 h.n_mvm = st.n_mvm;
-                h.precision = prec;
+                h.precision = corr ? CHEBFD_PREC_C64_CORRECTION : prec;
                 h.n_locked = n_lock;
                 h.n_converged = nconv;
                 h.n_accepted = nconv + nconving;
@@ -645,7 +718,8 @@ struct Solver {
                 std::fprintf(stderr,
                              "chebfd: iteration %d (%s) active %d locked %d converged %d "
                              "converging %d min in-window residual %.3e filter %.2f s\n",
-                             it, prec == CHEBFD_PREC_C64 ? "c64" : "c128", k, n_lock, nconv,
+                             it, corr ? "c64 correction" : prec == CHEBFD_PREC_C64 ? "c64" : "c128",
+                             k, n_lock, nconv,
                              nconving, rmin, secs(ta, tb));
                 std::fflush(stderr);
             }
@@ -738,7 +812,15 @@ struct Solver {
                         if ((rc = sync())) return rc;
                         std::swap(X, U);
                         ns_act = m;
+                        th_act.clear();
+                        for (int j : sel) th_act.push_back(theta[j]);
+                    } else {
+                        th_act.assign(theta.begin(), theta.begin() + k);
                     }
+                    // the coefficient table ((n_p + 1) x n_s doubles at most)
+                    // borrows a complex128 block during the correction pass
+                    corr = p.polish == CHEBFD_POLISH_CORRECTION &&
+                           (size_t)(p.n_p + 1) * ns * 8 <= L.blk64;
                     // the count to confirm is the number of in-window pairs
                     // the FP32 sweep brought below sqrt(eps)
                     prev_conv = ngood;
@@ -793,6 +875,21 @@ struct Solver {
                     if ((rc = sync())) return rc;
                     std::swap(X, U);
                 }
+            }
+            if (corr) {
+                // Ritz values of the columns that stay active (in X's order)
+                th_act.clear();
+                if (p.lock && !conv_idx.empty())
+                    for (int j : keep_idx) th_act.push_back(theta[j]);
+                else
+                    th_act.assign(theta.begin(), theta.begin() + k);
+                // a pass that neither converges a pair nor halves the largest
+                // accepted residual has met the correction's FP32 floor:
+                // FP64 passes from now on
+                const int cc = p.lock ? n_lock : nconv;
+                if (nconving > 0 && worst >= 0.5 * corr_worst && cc <= corr_conv) corr = false;
+                corr_worst = nconving > 0 ? worst : INFINITY;
+                corr_conv = cc;
             }
             const int total_conv = p.lock ? n_lock : nconv;
             const bool stagnant =
@@ -929,6 +1026,8 @@ static int check_params(const chebfd_matrix *H, const chebfd_params *p)
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: adapt must be 0 or 1");
     if (p->harmonic != 0 && (p->harmonic != 1 || !p->lock))
         return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: harmonic must be 0, or 1 with lock = 1");
+    if (p->polish != CHEBFD_POLISH_CORRECTION && p->polish != CHEBFD_POLISH_FP64)
+        return fail(CHEBFD_ERR_INVALID_ARG, "chebfd_solve: polish must be CORRECTION or FP64");
     return CHEBFD_OK;
 }
 

@@ -54,16 +54,18 @@ def problem(ctx, seed, L=L_DEFAULT, storage=B.STORAGE_STENCIL):
 
 
 def run_solve(ctx, H, delta, n_s, n_p, corr=None, precision=B.PREC_C128, max_iter=40, seed=1,
-              verbose=0, bounds=0, polish_switch=float("nan")):
+              verbose=0, bounds=0, polish_switch=float("nan"), polish=B.POLISH_CORRECTION):
     p = B.default_params(lam_lo=-delta, lam_hi=delta, n_s=n_s, n_p=n_p, eps=1e-9,
                          max_iter=max_iter, precision=precision, lock=1, seed=seed, vectors=0,
                          gamma_corr=corr, verbose=verbose, bounds=bounds,
-                         polish_switch=polish_switch)
+                         polish_switch=polish_switch, polish=polish)
     t0 = time.perf_counter()
     rc, ev, rs, _, st = B.chebfd_solve(ctx, H, p)
     dt = time.perf_counter() - t0
     return dict(rc=int(rc), time=dt, found=int(len(ev)), evals=ev, res=rs, n_mvm=st["n_mvm"],
-                iterations=st["iterations"])
+                iterations=st["iterations"], iterations_c64=st["iterations_c64"],
+                iterations_corr=st["iterations_corr"],
+                history=[(h["precision"], h["n_mvm"]) for h in st["history"]])
 
 
 # sweep grid around the rule (N_S = 3 N_T, eta-optimal N_p): search spaces

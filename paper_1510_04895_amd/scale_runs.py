@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--polish-units", type=float, default=None,
                     help="complex64 forms: FP64 switch threshold in units of 2^-23 S_w "
                          "(default: the library's, 8 units)")
+    ap.add_argument("--polish", default="correction", choices=["correction", "fp64"],
+                    help="complex64 forms: FP32 correction passes or FP64 filter passes")
     ap.add_argument("--bounds", default="gershgorin", choices=["gershgorin", "lanczos"],
                     help="spectral interval: Gershgorin or 40 Lanczos steps (checked by the solver)")
     ap.add_argument("--plan-only", action="store_true",
@@ -135,10 +137,14 @@ def main():
         torch.cuda.synchronize()
         r = learned.run_solve(ctx, H, delta, n_s, n_p, corr=corr, precision=prec,
                               max_iter=args.max_iter, seed=w["seeds"][0], verbose=1,
-                              bounds=lanczos_steps, polish_switch=polish_switch)
+                              bounds=lanczos_steps, polish_switch=polish_switch,
+                              polish=(B.POLISH_FP64 if args.polish == "fp64"
+                                      else B.POLISH_CORRECTION))
         row = dict(form=form, n_p=n_p, corrections=corr is not None, status=r["rc"],
-                   found=r["found"], time_s=r["time"],
+                   found=r["found"], time_s=r["time"], polish=args.polish,
                    n_mvm=r["n_mvm"], iterations=r["iterations"],
+                   iterations_c64=r["iterations_c64"], iterations_corr=r["iterations_corr"],
+                   history=r["history"],
                    max_residual=float(r["res"].max()) if r["found"] else None,
                    polish_units=args.polish_units)
         if form == "fp64":

@@ -60,6 +60,32 @@ def test_coeffs_match_reference(B, orc):
         assert np.abs(g1 - g2).max() < 1e-13
 
 
+@pytest.mark.parametrize("kind,n_p", [("lanczos", 120), ("jackson", 37), ("none", 2)])
+def test_coeffs_divided_match_definition(B, orc, kind, n_p):
+    """chebfd_coeffs_divided: q(y) = (p(y) - p(t)) / (y - t) for the filter
+    polynomial p (evaluated by the reference, Clenshaw in the scaled
+    variable) and the returned p(t), at points inside and outside the window
+    and at the interval ends; q itself is summed here from its coefficients
+    with T_n(y) = cos(n arccos y)."""
+    a, b = -7.5, 8.25
+    gam = orc.gamma(-0.4, 0.3, a, b, n_p, kind=kind)
+    ys = np.linspace(-0.999, 0.999, 41)
+    for lam in (-0.35, 0.0, 0.3, 1.7, -7.5, 8.25):
+        d, pt = B.chebfd_coeffs_divided(gam, a, b, lam)
+        assert d.shape == (n_p,)
+        assert abs(pt - orc.poly_eval(gam, a, b, lam)) < 1e-13
+        t = (2 * lam - a - b) / (b - a)
+        for y in ys:
+            if abs(y - t) < 1e-3:
+                continue
+            q = float(np.sum(d * np.cos(np.arange(n_p) * np.arccos(y))))
+            x = 0.5 * ((b - a) * y + a + b)
+            want = (orc.poly_eval(gam, a, b, x) - pt) / (y - t)
+            assert abs(q - want) < 1e-11 * (1.0 + abs(want)), (lam, y, q, want)
+    with pytest.raises(B.ChebFDError):
+        B.chebfd_coeffs_divided(gam[:2], a, b, 0.0)
+
+
 def test_coeffs_invalid_arguments(B):
     with pytest.raises(B.ChebFDError) as e:
         B.chebfd_coeffs(0.1, -0.1, -1, 1, 10)
