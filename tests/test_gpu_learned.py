@@ -114,10 +114,14 @@ def test_trained_model_on_heldout_realisation(env, seed):
     """The committed network on a held-out 32x32x16 realisation (seeds of
     the evaluation set, never trained on): its (N_p, N_S, corrections),
     gated by the damping-factor check, reach the same eigenvalues as the
-    DOS rule's parameters at residual <= 1e-9.  The work bound is a sanity
-    guard against a broken network or decoding (the held-out evaluation
-    saw ratios of matrix-vector products between 0.70 and 1.8 per
-    realisation), not a performance claim."""
+    DOS rule's parameters at residual <= 1e-9.
+
+    The network does not beat the rule.  On the 20 held-out realisations it
+    needs 1.5% more matrix-vector products in total than the rule (median
+    1.12x per realisation, range 0.85x-1.39x).  On the training sweep the
+    rule is the best fixed point of the (N_S, N_p) grid, and the best point
+    per realisation would save 12%, which the KPM features do not predict.
+    The work bound is only a guard against a broken network or decoding."""
     import os
     torch, B, ctx = env
     from paper_1510_04895_amd import learned
@@ -133,4 +137,4 @@ def test_trained_model_on_heldout_realisation(env, seed):
     if base["found"]:
         assert np.abs(lrn["evals"] - base["evals"]).max() < 1e-10 * S_w
         assert lrn["res"].max() <= 1e-9
-    assert lrn["n_mvm"] <= 2.0 * base["n_mvm"]
+    assert lrn["n_mvm"] <= 1.5 * base["n_mvm"]
