@@ -60,6 +60,13 @@ int main(void)
           "chebfd_coeffs");
     check(chebfd_filter_quality(gam, 300, -1.0, 1.0, -0.1, 0.1, -0.2, 0.2, &s, &e),
           "chebfd_filter_quality");
+    /* division by a linear factor: n_p coefficients into an exact-size heap
+       block, for the smallest and a large degree */
+    for (int npd = 2; npd <= 300; npd += 298) {
+        double *d = (double *)malloc(sizeof(double) * npd), pt;
+        check(chebfd_coeffs_divided(gam, npd, -1.0, 1.0, 0.05, d, &pt), "chebfd_coeffs_divided");
+        free(d);
+    }
     int nopt;
     check(chebfd_optimal_np(-1.0, 1.0, -0.05, 0.05, -0.1, 0.1, CHEBFD_KERNEL_LANCZOS, 2.0, 8,
                             400, &nopt, &e),

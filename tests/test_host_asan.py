@@ -1,7 +1,8 @@
 """The library's host math built with AddressSanitizer (host code only; no
 GPU code is instrumented) and driven through its C ABI: chebfd_dos_params
 over moment counts 4..512, the learned-form maps, the correction fit, the
-coefficient and quality rules and the dense eigensolver.  Any heap or stack
+coefficient and quality rules, the divided coefficients of the correction
+pass and the dense eigensolver.  Any heap or stack
 overflow aborts the driver."""
 import os
 import subprocess
