@@ -378,15 +378,15 @@ int launch_ti_lps(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t 
 
 }  // namespace
 
-int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb);
+int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb, bool stencil);
 
 int launch_stencil_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a,
                         int64_t *n_part)
 {
     const Stencil &S = H->st;
     if (a.precision == CHEBFD_PREC_C128)
-        return launch_ti_lps<double, 1>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 1));
-    return launch_ti_lps<float, 2>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 2));
+        return launch_ti_lps<double, 1>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 1, true));
+    return launch_ti_lps<float, 2>(ctx, S, a, n_part, pick_lpr(ctx, a.n_s, 2, true));
 }
 
 }  // namespace chebfd

@@ -789,14 +789,18 @@ int launch_sell_lpr(chebfd_ctx *ctx, const Sell &S, const StepArgs &a, int lpr)
 int launch_stencil_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a,
                         int64_t *n_part);
 
-// Lanes per row: the narrowest slab that still covers the block (fewer idle
-// lanes for thin blocks such as the KPM vectors), else the tuned width
-// (default 32 lanes = 512-byte row segments in c128).
-int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb)
+// Lanes per row (or per lattice site): the narrowest slab that still covers
+// the block (fewer idle lanes for thin blocks such as the KPM vectors), else
+// the tuned width, else 32 lanes (512-byte row segments in c128), and for
+// the matrix-free step in c64 with more than 32 packs a whole wave per site
+// (1 KB row segments: 16.4 against 17.5 ms per step at 256x256x64 with
+// 128 columns; in c128 32 lanes stay fastest).
+int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb, bool stencil)
 {
     const int64_t packs = (n_s + nb - 1) / nb;
     if (packs <= 16) return 16;
     if (ctx->tune_lpr == 16 || ctx->tune_lpr == 32 || ctx->tune_lpr == 64) return ctx->tune_lpr;
+    if (stencil && nb == 2 && packs > 32) return 64;
     return 32;
 }
 
@@ -805,7 +809,7 @@ int launch_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a, int6
     if (H->storage == CHEBFD_STORAGE_STENCIL) return launch_stencil_step(ctx, H, a, n_part);
     const Sell &S = H->sell;
     const int nb = a.precision == CHEBFD_PREC_C128 ? 1 : 2;
-    const int lpr = pick_lpr(ctx, a.n_s, nb);
+    const int lpr = pick_lpr(ctx, a.n_s, nb, false);
     if (n_part) *n_part = sell_row_blocks(S, lpr);
     if (a.precision == CHEBFD_PREC_C128) return launch_sell_lpr<double, 1>(ctx, S, a, lpr);
     return launch_sell_lpr<float, 2>(ctx, S, a, lpr);
@@ -815,7 +819,7 @@ int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int p
                             int64_t n_s)
 {
     const int nb = precision == CHEBFD_PREC_C128 ? 1 : 2;
-    const int lpr = pick_lpr(ctx, n_s, nb);
+    const int lpr = pick_lpr(ctx, n_s, nb, H->storage == CHEBFD_STORAGE_STENCIL);
     if (H->storage == CHEBFD_STORAGE_SELL) return sell_row_blocks(H->sell, lpr);
     // the larger of the two stencil block counts (site-linear and tiled;
     // strips of one column give the most tiled blocks)

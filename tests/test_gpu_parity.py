@@ -111,25 +111,31 @@ def test_filter_c128_vs_reference(env, orc, storage, n_s, ld, n_p):
 
 
 @pytest.mark.parametrize("storage", ["sell", "stencil"])
-def test_filter_c64_vs_reference(env, orc, storage):
+@pytest.mark.parametrize("n_s", [34, 130])
+def test_filter_c64_vs_reference(env, orc, storage, n_s):
+    """complex64 filter with moments; 130 columns (65 packs) take the
+    matrix-free step's whole-wave-per-site shape and a ragged pack."""
     torch, B, ctx = env
     L = (6, 6, 4)
     Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=4)
     a, b = orc.gershgorin(Hr)
     st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
     H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=4, storage=st)
-    n_s, n_p = 34, 60
+    n_p = 60
     X = inp.random_block(Hr.n, n_s, seed=8).astype(np.complex64).astype(np.complex128)
     gam = orc.gamma(-0.5, 0.5, a, b, n_p)
-    ref = orc.filter_block(Hr, a, b, gam, X)
+    ref, mref = orc.filter_block(Hr, a, b, gam, X, moments=True)
     Xd = to_dev(torch, X, dtype=torch.complex64)
     Ud = torch.zeros_like(Xd)
     Wd = torch.zeros_like(Xd)
-    B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd)
+    mom = torch.zeros((2 * n_p + 1, n_s), dtype=torch.float64, device="cuda")
+    B.chebfd_filter_apply(ctx, H, gam, a, b, Xd, Ud, Wd, moments=mom)
     torch.cuda.synchronize()
     got = Xd.cpu().numpy().astype(np.complex128)
     tol = 30 * math.sqrt(n_p) * 2.0 ** -24
     assert relerr(got, ref) < tol
+    assert np.abs(got - ref).max() / np.abs(ref).max() < tol
+    assert np.abs(mom.cpu().numpy() - mref).max() < 1e-4 * np.abs(mref[0]).max()
 
 
 @pytest.mark.parametrize("storage", ["sell", "stencil"])
