@@ -505,7 +505,8 @@ def _dense_window(orc, Hr, n_in):
 
 
 @pytest.mark.parametrize("storage,prec,lock", [("sell", "c128", 1), ("stencil", "c128", 0),
-                                               ("sell", "c64", 1), ("stencil", "c64", 1)])
+                                               ("sell", "c64", 1), ("stencil", "c64", 1),
+                                               ("sell", "c64", 0), ("stencil", "c64", 0)])
 def test_solve_small_lattice_vs_dense(env, orc, storage, prec, lock):
     torch, B, ctx = env
     L = (4, 4, 4)
@@ -836,6 +837,30 @@ def test_solve_harmonic_vs_golden(env, orc, seed):
         assert np.abs(V.conj().T @ V - np.eye(16)).max() < 1e-8
         ghosts[harm] = [h["n_window"] - h["n_accepted"] for h in stats["history"]]
     print(f"seed {seed}: in-window ghosts per iteration, harmonic {ghosts[1]}, Ritz {ghosts[0]}")
+
+
+def test_solve_harmonic_precision_form_vs_golden(env, orc):
+    """Harmonic extraction in the precision form: the complex64 sweep, then
+    FP32 correction passes on the harmonic pairs (their Rayleigh quotients
+    as the division points), return the 16 dense-oracle eigenvalues with
+    orthonormal vectors whose residuals the oracle recomputes."""
+    torch, B, ctx = env
+    w = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "ti_8x8x8_V1_seed2_evals.txt"))
+    aw = np.sort(np.abs(w))
+    d = 0.5 * (aw[15] + aw[16])
+    want = np.sort(w[np.abs(w) <= d])
+    H = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=2)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=32, n_p=200, eps=1e-9, seed=1002,
+                         max_iter=200, harmonic=1, precision=B.PREC_C64)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    assert rc == 0 and ev.size == 16, (rc, ev, stats)
+    assert np.abs(ev - want).max() < 1e-10 * S_w
+    assert stats["iterations_corr"] >= 1
+    Hr = orc.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=2)
+    r = np.linalg.norm(orc.spmm(Hr, V) - V * ev, axis=0)
+    assert r.max() <= 1.05e-9
+    assert np.abs(V.conj().T @ V - np.eye(16)).max() < 1e-8
 
 
 def test_solve_harmonic_matches_oracle_harmonic(env, orc):
