@@ -83,24 +83,31 @@ XCDS = 8                    # GRBM_GUI_ACTIVE arrives summed over the 8 XCDs
 
 def mfma(pmc_dir, name, cmd, kernels=("k_gram", "k_block_times")):
     vals = collections.defaultdict(list)
+    per_disp = collections.defaultdict(float)   # (kernel, dispatch) -> MFMA ops
     with open(_csv_in(pmc_dir)) as fh:
         for r in csv.DictReader(fh):
             vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+            if r["Counter_Name"] == "SQ_INSTS_VALU_MFMA_MOPS_F64":
+                per_disp[(r["Kernel_Name"], r["Dispatch_Id"])] += float(r["Counter_Value"])
     lines = [f"# {name}", "", "Command (from the repository root, TMPDIR=/tmp):", "",
              "    " + cmd, "",
-             "| kernel | dispatches | FP64 MFMA flops per dispatch | MFMA busy, % of SIMD cycles |",
-             "|---|---:|---:|---:|"]
+             "| kernel | dispatches | FP64 MFMA flops per dispatch (mean) | largest dispatch | "
+             "MFMA busy, % of SIMD cycles |",
+             "|---|---:|---:|---:|---:|"]
     out = {}
     for (k, c), v in sorted(vals.items()):
         if c != "SQ_INSTS_VALU_MFMA_MOPS_F64" or not any(s in k for s in kernels):
             continue
         busy = sum(vals[(k, "SQ_VALU_MFMA_BUSY_CYCLES")])
         gui = sum(vals[(k, "GRBM_GUI_ACTIVE")])
-        flops = sum(v) * 512 / len(v)
+        disp = [f for (kk, _), f in per_disp.items() if kk == k]
+        flops = sum(disp) * 512 / len(disp)
+        fmax = max(disp) * 512
         util = 100.0 * busy / (gui / XCDS * SIMDS) if gui > 0 else float("nan")
         nm = k.replace("chebfd::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
-        out[nm] = dict(dispatches=len(v), flops_per_dispatch=flops, mfma_busy_pct=util)
-        lines.append(f"| `{nm}` | {len(v)} | {flops:.3e} | {util:.1f} |")
+        out[nm] = dict(dispatches=len(disp), flops_per_dispatch=flops, flops_max=fmax,
+                       mfma_busy_pct=util)
+        lines.append(f"| `{nm}` | {len(disp)} | {flops:.4e} | {fmax:.4e} | {util:.1f} |")
     text = "\n".join(lines) + "\n"
     with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as fh:
         fh.write(text)

@@ -12,12 +12,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _write_pmc(d, rows):
+    """rocprofv3 counter CSV rows (kernel, counter, value), one dispatch each."""
     os.makedirs(d, exist_ok=True)
     with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as fh:
-        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
         w.writeheader()
-        for k, c, v in rows:
-            w.writerow(dict(Kernel_Name=k, Counter_Name=c, Counter_Value=v))
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow(dict(Dispatch_Id=i + 1, Kernel_Name=k, Counter_Name=c, Counter_Value=v))
 
 
 def test_traffic_calibration(tmp_path, monkeypatch):
@@ -119,5 +121,6 @@ def test_mfma_summary(tmp_path, monkeypatch):
     out = ps.mfma(str(tmp_path / "m"), "mfma_test", "cmd")
     assert list(out) == ["k_gram<double>"]
     assert out["k_gram<double>"]["flops_per_dispatch"] == pytest.approx(2000 * 512)
+    assert out["k_gram<double>"]["flops_max"] == pytest.approx(3000 * 512)
     assert out["k_gram<double>"]["mfma_busy_pct"] == pytest.approx(40.0)
     assert "| `k_gram<double>` | 2 |" in open(tmp_path / "profiles" / "mfma_test.md").read()
