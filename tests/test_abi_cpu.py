@@ -98,6 +98,23 @@ def test_coeffs_invalid_arguments(B):
         B.chebfd_coeffs(-0.1, 0.1, 1, -1, 10)
 
 
+def test_filter_columns_rejects_bad_arguments_without_a_device(B):
+    """chebfd_filter_apply_columns checks its arguments before any device
+    call: NULL context, matrix or table -> INVALID_ARG; complex128 ->
+    UNSUPPORTED (the per-column step exists for complex64 only)."""
+    L = B.lib()
+    dummy = C.c_void_p(8)
+    assert L.chebfd_filter_apply_columns(None, dummy, B.PREC_C64, dummy, 4, 10, -1.0, 1.0,
+                                         dummy, dummy, dummy, 4, 4) == -1
+    assert L.chebfd_filter_apply_columns(dummy, None, B.PREC_C64, dummy, 4, 10, -1.0, 1.0,
+                                         dummy, dummy, dummy, 4, 4) == -1
+    assert L.chebfd_filter_apply_columns(dummy, dummy, B.PREC_C64, None, 4, 10, -1.0, 1.0,
+                                         dummy, dummy, dummy, 4, 4) == -1
+    assert L.chebfd_filter_apply_columns(dummy, dummy, B.PREC_C128, dummy, 4, 10, -1.0, 1.0,
+                                         dummy, dummy, dummy, 4, 4) == -5
+    assert b"complex64" in L.chebfd_last_error()
+
+
 def test_filter_quality_matches_reference(B, orc):
     g = orc.gamma(-0.0025, 0.0025, -1, 1, 817)
     s1, e1 = B.chebfd_filter_quality(g, -1, 1, -0.0025, 0.0025, -0.01, 0.01)
