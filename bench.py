@@ -115,13 +115,31 @@ def cpu_baseline(L, n_s, target_s=15.0, max_steps=400):
     dt = time.perf_counter() - t0
     vb = H.nnz * 20 + 5 * H.n * n_s * 16
     model, mem = host_info()
+    # the oracle's complete solve (Sec. 3.1 steps 1-8) of the 8x8x8
+    # correctness configuration, beside the library's time_to_solution entry
+    w8, d8 = solve_8x8x8_window()
+    H8 = oracle.ti_hamiltonian(8, 8, 8, pbc=3, V=1.0, seed=1)
+    t0 = time.perf_counter()
+    rc8, ev8, _, _, _ = oracle.chebfd_solve(H8, -d8, d8, 32, 200, seed=1001, vectors=False)
+    t8 = time.perf_counter() - t0
+    solve8 = dict(time_to_solution_s=round(t8, 3), status=int(rc8), eigenpairs_found=int(ev8.size),
+                  config="8x8x8, window of the 16 dense eigenvalues nearest 0, n_s 32, n_p 200, "
+                         "Gershgorin bounds, FP64")
     return dict(value=round(n_steps * vb / dt / 1e9, 3), unit="GB/s", cores=oracle.num_threads(),
-                kind="oracle", cpu_model=model, host_mem_gib=mem,
+                kind="oracle", cpu_model=model, host_mem_gib=mem, solve_8x8x8=solve8,
                 sample=f"filter of degree {n_steps} ({n_steps} recurrence steps of Fig. "
                        f"fig:ChebFD, CSR, OpenMP static) on the {Ls[0]}x{Ls[1]}x{Ls[2]} slab of "
                        f"the lattice (N={H.n}), n_s={n_s}, c128, {dt:.1f} s on "
                        f"{oracle.num_threads()} threads; bytes per step nnz*20 + 5*N*n_s*16, "
                        f"as for the GPU figure")
+
+
+def solve_8x8x8_window():
+    """The golden dense spectrum of the 8x8x8 lattice (seed 1) and the
+    half-width that holds its 16 eigenvalues nearest 0."""
+    w = np.loadtxt(os.path.join(ROOT, "tests", "golden", "ti_8x8x8_V1_seed1_evals.txt"))
+    aw = np.sort(np.abs(w))
+    return w, 0.5 * (aw[15] + aw[16])
 
 
 def launch_bytes(mat, n, n_s, s_d, k):
@@ -363,6 +381,27 @@ def main():
             r2["matches_oracle_window"] = bool(g.size == ev2.size and
                                                np.abs(g - ev2).max() < 1e-10 * S2)
         tts["ti_64x64x32_fp64"] = r2
+        # the 8x8x8 correctness configuration (the CPU leg times the
+        # oracle's solve of the same configuration)
+        w8, d8 = solve_8x8x8_window()
+        H8 = B.Matrix.ti(ctx, (8, 8, 8), pbc=3, V=1.0, seed=1, storage=(B.STORAGE_SELL if args.storage == "sell"
+                                          else B.STORAGE_STENCIL))
+        p8 = B.default_params(lam_lo=-d8, lam_hi=d8, n_s=32, n_p=200, eps=1e-9, seed=1001,
+                              vectors=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc8, ev8, rs8, _, st8 = B.chebfd_solve(ctx, H8, p8)
+        torch.cuda.synchronize()
+        t8 = time.perf_counter() - t0
+        want = np.sort(w8[np.abs(w8) <= d8])
+        S8 = max(abs(st8["a"]), abs(st8["b"]))
+        tts["ti_8x8x8_fp64"] = {
+            "time_to_solution_s": round(t8, 4), "status": int(rc8),
+            "eigenpairs_found": int(ev8.size), "iterations": st8["iterations"],
+            "max_residual": float(rs8.max()) if rs8.size else None,
+            "matches_dense_oracle": bool(ev8.size == want.size and
+                                         np.abs(ev8 - want).max() < 1e-10 * S8)}
+        del H8
         out["time_to_solution"] = tts
     out["roofline"] = roof
     out["bandwidth_probe_gbs"] = {"read_only": round(probe[0], 1), "copy": round(probe[1], 1),

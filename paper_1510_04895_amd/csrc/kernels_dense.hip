@@ -11,6 +11,7 @@
 // Likewise A T (complex T) equals Z_A Treal with Treal[2k][2l] = Re T,
 // Treal[2k][2l+1] = Im T, Treal[2k+1][2l] = -Im T, Treal[2k+1][2l+1] = Re T.
 // Both are therefore plain real FP64 contractions on v_mfma_f64_16x16x4_f64.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -262,41 +263,56 @@ template <typename T>
 __global__ void k_random(T *X, int64_t n, int64_t n_s, int64_t ld, int64_t k0, int64_t m,
                          uint64_t key, uint64_t offset)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * m) return;
-    const int64_t i = idx / m, k = k0 + (idx - (idx / m) * m);
-    const uint64_t e = offset + (uint64_t)(i * n_s + k);
-    const double re = 2.0 * du01(key, 2 * e) - 1.0;
-    const double im = 2.0 * du01(key, 2 * e + 1) - 1.0;
-    X[2 * (i * ld + k)] = (T)re;
-    X[2 * (i * ld + k) + 1] = (T)im;
+    const int64_t total = n * m, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += stride) {
+        const int64_t i = idx / m, k = k0 + (idx - (idx / m) * m);
+        const uint64_t e = offset + (uint64_t)(i * n_s + k);
+        const double re = 2.0 * du01(key, 2 * e) - 1.0;
+        const double im = 2.0 * du01(key, 2 * e + 1) - 1.0;
+        X[2 * (i * ld + k)] = (T)re;
+        X[2 * (i * ld + k) + 1] = (T)im;
+    }
 }
 
 template <typename T>
 __global__ void k_phase(T *X, int64_t n, int64_t n_s, int64_t ld, uint64_t key)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n_s) return;
-    const int64_t i = idx / n_s, k = idx - (idx / n_s) * n_s;
-    const double u = du01(key, (uint64_t)idx);
-    double s, c;
-    sincospi(2.0 * u, &s, &c);
-    X[2 * (i * ld + k)] = (T)c;
-    X[2 * (i * ld + k) + 1] = (T)s;
+    const int64_t total = n * n_s, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += stride) {
+        const int64_t i = idx / n_s, k = idx - (idx / n_s) * n_s;
+        const double u = du01(key, (uint64_t)idx);
+        double s, c;
+        sincospi(2.0 * u, &s, &c);
+        X[2 * (i * ld + k)] = (T)c;
+        X[2 * (i * ld + k) + 1] = (T)s;
+    }
 }
 
 template <typename TI, typename TO>
 __global__ void k_convert(const TI *__restrict__ X, TO *__restrict__ Y, int64_t n, int64_t n_s,
                           int64_t ld_in, int64_t ld_out)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n_s) return;
-    const int64_t i = idx / n_s, k = idx - (idx / n_s) * n_s;
-    Y[2 * (i * ld_out + k)] = (TO)X[2 * (i * ld_in + k)];
-    Y[2 * (i * ld_out + k) + 1] = (TO)X[2 * (i * ld_in + k) + 1];
+    const int64_t total = n * n_s, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += stride) {
+        const int64_t i = idx / n_s, k = idx - (idx / n_s) * n_s;
+        Y[2 * (i * ld_out + k)] = (TO)X[2 * (i * ld_in + k)];
+        Y[2 * (i * ld_out + k) + 1] = (TO)X[2 * (i * ld_in + k) + 1];
+    }
 }
 
 inline unsigned nblocks(int64_t total, int per) { return (unsigned)((total + per - 1) / per); }
+
+// Grid of the element-wise kernels (one element per lane, grid-stride): a
+// dispatch holds fewer than 2^32 work-items, and a block of N x N_S
+// elements can hold more (N = 2^24 rows, N_S = 256), so the grid is capped
+// at 2^20 workgroups of 256 lanes and each lane strides over the rest.
+inline unsigned elem_grid(int64_t total)
+{
+    return (unsigned)std::min<int64_t>((total + 255) / 256, (int64_t)1 << 20);
+}
 
 // Scaled residual block of the correction pass, rounded to complex64:
 // R[:, j] = HV[:, j] - t_j V[:, j] for j < k (HV the scaled product
@@ -305,17 +321,19 @@ __global__ void k_defect(const double *__restrict__ V, const double *__restrict_
                          const double *__restrict__ t, float *__restrict__ R, int64_t n,
                          int64_t k, int64_t kk, int64_t ld_v, int64_t ld_r)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * kk) return;
-    const int64_t i = idx / kk, j = idx - (idx / kk) * kk;
-    float re = 0.0f, im = 0.0f;
-    if (j < k) {
-        const double *v = V + 2 * (i * ld_v + j), *h = HV + 2 * (i * ld_v + j);
-        re = (float)__builtin_fma(-t[j], v[0], h[0]);
-        im = (float)__builtin_fma(-t[j], v[1], h[1]);
+    const int64_t total = n * kk, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += stride) {
+        const int64_t i = idx / kk, j = idx - (idx / kk) * kk;
+        float re = 0.0f, im = 0.0f;
+        if (j < k) {
+            const double *v = V + 2 * (i * ld_v + j), *h = HV + 2 * (i * ld_v + j);
+            re = (float)__builtin_fma(-t[j], v[0], h[0]);
+            im = (float)__builtin_fma(-t[j], v[1], h[1]);
+        }
+        R[2 * (i * ld_r + j)] = re;
+        R[2 * (i * ld_r + j) + 1] = im;
     }
-    R[2 * (i * ld_r + j)] = re;
-    R[2 * (i * ld_r + j) + 1] = im;
 }
 
 // V[:, j] = p_j V[:, j] + D[:, j] (D complex64), j < k.
@@ -323,13 +341,15 @@ __global__ void k_combine(double *__restrict__ V, const float *__restrict__ D,
                           const double *__restrict__ pt, int64_t n, int64_t k, int64_t ld_v,
                           int64_t ld_d)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * k) return;
-    const int64_t i = idx / k, j = idx - (idx / k) * k;
-    double *v = V + 2 * (i * ld_v + j);
-    const float *d = D + 2 * (i * ld_d + j);
-    v[0] = __builtin_fma(pt[j], v[0], (double)d[0]);
-    v[1] = __builtin_fma(pt[j], v[1], (double)d[1]);
+    const int64_t total = n * k, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += stride) {
+        const int64_t i = idx / k, j = idx - (idx / k) * k;
+        double *v = V + 2 * (i * ld_v + j);
+        const float *d = D + 2 * (i * ld_d + j);
+        v[0] = __builtin_fma(pt[j], v[0], (double)d[0]);
+        v[1] = __builtin_fma(pt[j], v[1], (double)d[1]);
+    }
 }
 
 // Attainable-bandwidth probes (the read-only reduction of Sec. 4.1, a copy,
@@ -425,12 +445,13 @@ __global__ void k_gather_cols(const T *__restrict__ src, int64_t lds, T *__restr
                               int64_t ldd, int64_t d0, const int32_t *__restrict__ idx, int64_t n,
                               int64_t m)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * m) return;
-    const int64_t i = t / m, j = t - (t / m) * m;
-    const int64_t s = 2 * (i * lds + idx[j]), d = 2 * (i * ldd + d0 + j);
-    dst[d] = src[s];
-    dst[d + 1] = src[s + 1];
+    const int64_t total = n * m, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t i = t / m, j = t - (t / m) * m;
+        const int64_t s = 2 * (i * lds + idx[j]), d = 2 * (i * ldd + d0 + j);
+        dst[d] = src[s];
+        dst[d + 1] = src[s + 1];
+    }
 }
 
 }  // namespace
@@ -522,10 +543,10 @@ int launch_random(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_s, in
     const uint64_t key = mix64(seed + 0x9E3779B97F4A7C15ULL * (stream + 1u));
     if (n * m == 0) return CHEBFD_OK;
     if (prec == CHEBFD_PREC_C128)
-        hipLaunchKernelGGL(k_random<double>, dim3(nblocks(n * m, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_random<double>, dim3(elem_grid(n * m)), dim3(256), 0,
                            ctx->stream, (double *)X, n, n_s, ld, k0, m, key, offset);
     else
-        hipLaunchKernelGGL(k_random<float>, dim3(nblocks(n * m, 256)), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(k_random<float>, dim3(elem_grid(n * m)), dim3(256), 0, ctx->stream,
                            (float *)X, n, n_s, ld, k0, m, key, offset);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
@@ -545,11 +566,11 @@ int launch_gather_cols(chebfd_ctx *ctx, int prec, const void *src, int64_t lds, 
 {
     if (n * m == 0) return CHEBFD_OK;
     if (prec == CHEBFD_PREC_C128)
-        hipLaunchKernelGGL(k_gather_cols<double>, dim3(nblocks(n * m, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_gather_cols<double>, dim3(elem_grid(n * m)), dim3(256), 0,
                            ctx->stream, (const double *)src, lds, (double *)dst, ldd, d0, idx_dev,
                            n, m);
     else
-        hipLaunchKernelGGL(k_gather_cols<float>, dim3(nblocks(n * m, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_gather_cols<float>, dim3(elem_grid(n * m)), dim3(256), 0,
                            ctx->stream, (const float *)src, lds, (float *)dst, ldd, d0, idx_dev,
                            n, m);
     CHEBFD_CHECK_LAUNCH();
@@ -598,11 +619,12 @@ int launch_phase_block(chebfd_ctx *ctx, int prec, void *X, int64_t n, int64_t n_
                        uint64_t seed, uint64_t stream)
 {
     const uint64_t key = mix64(seed + 0x9E3779B97F4A7C15ULL * (stream + 1u));
+    if (n * n_s == 0) return CHEBFD_OK;
     if (prec == CHEBFD_PREC_C128)
-        hipLaunchKernelGGL(k_phase<double>, dim3(nblocks(n * n_s, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_phase<double>, dim3(elem_grid(n * n_s)), dim3(256), 0,
                            ctx->stream, (double *)X, n, n_s, ld, key);
     else
-        hipLaunchKernelGGL(k_phase<float>, dim3(nblocks(n * n_s, 256)), dim3(256), 0,
+        hipLaunchKernelGGL(k_phase<float>, dim3(elem_grid(n * n_s)), dim3(256), 0,
                            ctx->stream, (float *)X, n, n_s, ld, key);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
@@ -612,7 +634,7 @@ int launch_defect(chebfd_ctx *ctx, const void *V, const void *HV, const double *
                   int64_t n, int64_t k, int64_t kk, int64_t ld_v, int64_t ld_r)
 {
     if (n * kk == 0) return CHEBFD_OK;
-    hipLaunchKernelGGL(k_defect, dim3(nblocks(n * kk, 256)), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL(k_defect, dim3(elem_grid(n * kk)), dim3(256), 0, ctx->stream,
                        (const double *)V, (const double *)HV, t_dev, (float *)R, n, k, kk, ld_v,
                        ld_r);
     CHEBFD_CHECK_LAUNCH();
@@ -623,7 +645,7 @@ int launch_combine(chebfd_ctx *ctx, void *V, const void *D, const double *p_dev,
                    int64_t k, int64_t ld_v, int64_t ld_d)
 {
     if (n * k == 0) return CHEBFD_OK;
-    hipLaunchKernelGGL(k_combine, dim3(nblocks(n * k, 256)), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL(k_combine, dim3(elem_grid(n * k)), dim3(256), 0, ctx->stream,
                        (double *)V, (const float *)D, p_dev, n, k, ld_v, ld_d);
     CHEBFD_CHECK_LAUNCH();
     return CHEBFD_OK;
@@ -632,7 +654,8 @@ int launch_combine(chebfd_ctx *ctx, void *V, const void *D, const double *p_dev,
 int launch_convert(chebfd_ctx *ctx, int prec_in, const void *X, int prec_out, void *Y, int64_t n,
                    int64_t n_s, int64_t ld_in, int64_t ld_out)
 {
-    const unsigned g = nblocks(n * n_s, 256);
+    if (n * n_s == 0) return CHEBFD_OK;
+    const unsigned g = elem_grid(n * n_s);
     if (prec_in == CHEBFD_PREC_C128 && prec_out == CHEBFD_PREC_C64)
         hipLaunchKernelGGL((k_convert<double, float>), dim3(g), dim3(256), 0, ctx->stream,
                            (const double *)X, (float *)Y, n, n_s, ld_in, ld_out);

@@ -314,8 +314,9 @@ int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n
     const int64_t nblk = order == 1 ? (int64_t)(S.L[0] / tile) * S.L[1] * bpr
                                     : (nsites + SPB - 1) / SPB;
     const int64_t nslab = (a.n_s + SW - 1) / SW;
-    if (nblk * nslab >= ((int64_t)1 << 31))
-        return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
+    // a dispatch holds fewer than 2^32 work-items: < 2^24 workgroups of 256
+    if (nblk * nslab >= ((int64_t)1 << 24))
+        return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: more than 2^24 workgroups");
     if (n_part) *n_part = nblk;
     // default placement in the tiled order: one strip of blocks per XCD group
     int lg_xg = ilog2(ctx->tune_xcd_group);

@@ -682,8 +682,10 @@ int sell_geom(const chebfd_ctx *ctx, const Sell &S, const StepArgs &a, SellGeom 
     constexpr int RPP = rows_per_block<LPR>();
     const int64_t nslab = (a.n_s + SW - 1) / SW;
     const int64_t nrb = sell_row_blocks(S, LPR);
-    if (nrb * nslab >= ((int64_t)1 << 31) || a.ld * 16 >= ((int64_t)1 << 32))
-        return fail(CHEBFD_ERR_UNSUPPORTED, "fused step: block too large for 32-bit indexing");
+    // a dispatch holds fewer than 2^32 work-items: < 2^24 workgroups of 256
+    if (nrb * nslab >= ((int64_t)1 << 24) || a.ld * 16 >= ((int64_t)1 << 32))
+        return fail(CHEBFD_ERR_UNSUPPORTED,
+                    "fused step: more than 2^24 workgroups or a row stride above 2^32 bytes");
     const int units = S.C / S.group;   // rows or row groups per chunk
     g.RB = units < RPP ? units : RPP;
     g.lg_bpc = ilog2(units / g.RB);

@@ -201,3 +201,29 @@ def test_adaptive_degree_full_size(env, orc):
     print(f"64x64x32 adaptive: n_p 100 -> {stats['n_p_used']}, N_T estimate "
           f"{stats['n_t_estimate']:.1f}, {stats['iterations']} iterations, "
           f"{stats['t_total']:.2f} s")
+
+
+def test_random_block_and_convert_beyond_2_32_elements(env, orc):
+    """Blocks of more than 2^32 entries (here (2^25 + 3) x 128 complex64,
+    34 GB, then its complex128 copy, 69 GB): a dispatch holds fewer than
+    2^32 work-items, so the element-wise kernels stride over a capped grid.
+    Rows at the start, around 2^24 and at the end equal the reference
+    generator bit for bit, before and after the conversion."""
+    torch, B, ctx, _ = env
+    torch.cuda.empty_cache()
+    n, n_s, seed = (1 << 25) + 3, 128, 17
+    assert n * n_s > 2**32
+    X = torch.empty((n, n_s), dtype=torch.complex64, device="cuda")
+    B.chebfd_random_block(ctx, X, seed=seed)
+    Y = torch.empty((n, n_s), dtype=torch.complex128, device="cuda")
+    B.chebfd_convert(ctx, X, Y)
+    torch.cuda.synchronize()
+    try:
+        for i0 in (0, (1 << 24) - 1, (1 << 25) - 1, n - 2):
+            ref = orc.random_block(2, n_s, seed=seed, stream=1, offset=i0 * n_s)
+            got = X[i0:i0 + 2].cpu().numpy()
+            assert np.array_equal(got, ref.astype(np.complex64)), i0
+            assert np.array_equal(Y[i0:i0 + 2].cpu().numpy(), got.astype(np.complex128)), i0
+    finally:
+        del X, Y
+        torch.cuda.empty_cache()
