@@ -269,7 +269,9 @@ int chebfd_kpm_moments(chebfd_ctx *ctx, const chebfd_matrix *H, int precision, i
 
 /* Launch configuration of the fused filter step for this context:
  *   "lanes"       lanes sharing one row (SELL) or site (stencil): 16, 32, 64,
- *                 0 = default (32; 16 for blocks of at most 16 packs);
+ *                 0 = default (32; 16 for blocks of at most 16 packs; 64,
+ *                 a whole wave per site, for the matrix-free step in
+ *                 complex64 with more than 32 packs);
  *   "nontemporal" 1 (default) = streamed blocks w, x bypass cache retention;
  *   "order"       matrix-free lattice only: -1 (default) = automatic: the
  *                 tiled lattice order when, column-slab major, the bytes

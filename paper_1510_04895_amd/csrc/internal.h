@@ -133,6 +133,15 @@ struct StepArgs {
     int64_t ldg;
 };
 
+// Launch shape of the matrix-free step (order 0 column-slab major, 1 tiled
+// with strips of tile x-columns; nblk workgroups per slab).
+struct TiShape {
+    int order = 0, tile = 1;
+    int64_t bpr = 0, nblk = 0;
+};
+TiShape ti_shape(const chebfd_ctx *ctx, const Stencil &S, int64_t n_s, int elem, int nb, int lps);
+int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb, bool stencil);
+
 // Launches one fused step; returns number of partial-sum rows written
 // (per column triples) in *n_part when partials != nullptr.
 int launch_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a, int64_t *n_part);

@@ -284,35 +284,14 @@ __global__ __launch_bounds__(256) void k_step_ti(int Lx, int Ly, int Lz, int pbc
     }
 }
 
-// Default block order.  Column-slab major, a site is gathered as the
-// z-neighbour of the plane above and, two planes of work later, of the plane
-// below; in between the step moves two planes of its five block streams over
-// one slab.  Once that exceeds the memory-side cache (256 MB on MI355X) the
-// second gather goes back to HBM, and the tiled order (strips of x-columns,
-// z fastest: every neighbour at most one strip-row of work away, one strip
-// per XCD) wins: 256x256x64 with 128 columns in complex128, 38.0 ms
-// slab-major against 29.3 ms tiled.
-template <typename T, int SW>
-int auto_order(const Stencil &S, int64_t n_s)
-{
-    return tiled_order_pays(S.L, (int64_t)(n_s < SW ? n_s : SW) * 2 * sizeof(T)) ? 1 : 0;
-}
-
 template <typename T, int LPS, int NB, int MODE, bool MOM, bool NT, bool PC = false>
 int launch_ti_t(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t *n_part)
 {
-    constexpr int SPB = 4 * (64 / LPS);
     constexpr int SW = LPS * NB;
     const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
-    int order = ctx->tune_order >= 0 ? ctx->tune_order : auto_order<T, SW>(S, a.n_s);
-    // tiled order: the largest strip width up to the default that divides Lx
-    int tile = std::min(default_tile(ctx, false), S.L[0]);
-    while (tile > 1 && S.L[0] % tile) --tile;
-    if (order == 1 && tile < 1) order = 0;
-    // tiled blocks: SPB consecutive sites of a strip row (the last ragged)
-    const int64_t bpr = ((int64_t)tile * S.L[2] + SPB - 1) / SPB;
-    const int64_t nblk = order == 1 ? (int64_t)(S.L[0] / tile) * S.L[1] * bpr
-                                    : (nsites + SPB - 1) / SPB;
+    const TiShape g = ti_shape(ctx, S, a.n_s, (int)sizeof(T), NB, LPS);
+    const int order = g.order, tile = g.tile;
+    const int64_t bpr = g.bpr, nblk = g.nblk;
     const int64_t nslab = (a.n_s + SW - 1) / SW;
     // a dispatch holds fewer than 2^32 work-items: < 2^24 workgroups of 256
     if (nblk * nslab >= ((int64_t)1 << 24))
@@ -379,7 +358,34 @@ int launch_ti_lps(chebfd_ctx *ctx, const Stencil &S, const StepArgs &a, int64_t 
 
 }  // namespace
 
-int pick_lpr(const chebfd_ctx *ctx, int64_t n_s, int nb, bool stencil);
+// Launch shape of the matrix-free step for a block of n_s columns with
+// LPS lanes per site (NB columns of elem bytes per lane).
+//
+// Default block order.  Column-slab major, a site is gathered as the
+// z-neighbour of the plane above and, two planes of work later, of the plane
+// below; in between the step moves two planes of its five block streams over
+// one slab.  Once that exceeds the memory-side cache (256 MB on MI355X) the
+// second gather goes back to HBM, and the tiled order (strips of x-columns,
+// z fastest: every neighbour at most one strip-row of work away, one strip
+// per XCD) wins: 256x256x64 with 128 columns in complex128, 38.0 ms
+// slab-major against 29.3 ms tiled.
+TiShape ti_shape(const chebfd_ctx *ctx, const Stencil &S, int64_t n_s, int elem, int nb, int lps)
+{
+    TiShape g;
+    const int spb = 4 * (64 / lps), sw = lps * nb;
+    const int64_t row_bytes = (n_s < sw ? n_s : sw) * 2 * (int64_t)elem;
+    g.order = ctx->tune_order >= 0 ? ctx->tune_order : (tiled_order_pays(S.L, row_bytes) ? 1 : 0);
+    // tiled order: the largest strip width up to the default that divides Lx
+    g.tile = std::min(default_tile(ctx, false), S.L[0]);
+    while (g.tile > 1 && S.L[0] % g.tile) --g.tile;
+    if (g.order == 1 && g.tile < 1) g.order = 0;
+    // tiled blocks: spb consecutive sites of a strip row (the last ragged)
+    g.bpr = ((int64_t)g.tile * S.L[2] + spb - 1) / spb;
+    const int64_t nsites = (int64_t)S.L[0] * S.L[1] * S.L[2];
+    g.nblk = g.order == 1 ? (int64_t)(S.L[0] / g.tile) * S.L[1] * g.bpr
+                          : (nsites + spb - 1) / spb;
+    return g;
+}
 
 int launch_stencil_step(chebfd_ctx *ctx, const chebfd_matrix *H, const StepArgs &a,
                         int64_t *n_part)

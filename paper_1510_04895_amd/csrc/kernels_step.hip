@@ -823,13 +823,8 @@ int64_t step_partial_blocks(const chebfd_ctx *ctx, const chebfd_matrix *H, int p
     const int nb = precision == CHEBFD_PREC_C128 ? 1 : 2;
     const int lpr = pick_lpr(ctx, n_s, nb, H->storage == CHEBFD_STORAGE_STENCIL);
     if (H->storage == CHEBFD_STORAGE_SELL) return sell_row_blocks(H->sell, lpr);
-    // the larger of the two stencil block counts (site-linear and tiled;
-    // strips of one column give the most tiled blocks)
-    const Stencil &T = H->st;
-    const int64_t spb = 4 * (64 / lpr);
-    const int64_t lin = (H->n / 4 + spb - 1) / spb;
-    const int64_t tl = (int64_t)T.L[0] * T.L[1] * ((T.L[2] + spb - 1) / spb);
-    return std::max(lin, tl);
+    // the matrix-free step writes one partial row per workgroup of a slab
+    return ti_shape(ctx, H->st, n_s, precision == CHEBFD_PREC_C128 ? 8 : 4, nb, lpr).nblk;
 }
 
 int launch_moment_finalize(chebfd_ctx *ctx, const double *partials, int64_t n_part,

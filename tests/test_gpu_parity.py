@@ -329,7 +329,8 @@ def test_launch_settings_give_identical_blocks(env, storage):
         settings = [(-1, dict()), (-1, dict(lanes=64)), (-1, dict(lanes=16)),
                     (-1, dict(xcd_group=1)), (-1, dict(order=0)), (-1, dict(order=1)),
                     (2, dict(order=1, lanes=64)), (16, dict(order=1, xcd_group=1)),
-                    (4, dict(order=1, lanes=16)), (-1, dict(order=1, nontemporal=0))]
+                    (4, dict(order=1, lanes=16)), (-1, dict(order=1, nontemporal=0)),
+                    (8, dict(order=1, lanes=64))]
     defaults = dict(lanes=0, order=-1, xcd_group=0, nontemporal=1, pair_rows=1, row_group=-1,
                     slabs=0)
     outs, moms = [], []
