@@ -191,8 +191,12 @@ def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
     from the workload table; returns a summary dict and the eigenvalues."""
     w = inp.WORKLOADS[wname]
     st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
     H = B.Matrix.ti(ctx, w["L"], pbc=w["pbc"], V=w["V"], seed=w["seeds"][0], storage=st,
                     sell_C=w.get("sell_C", 32), sell_sigma=w.get("sell_sigma", 256))
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - tb
     info = H.info()
     steps = 40 if bounds == "lanczos" else 0
     a, b = (B.chebfd_lanczos_bounds(ctx, H, k=40, seed=w["seeds"][0]) if steps
@@ -214,7 +218,8 @@ def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
            "precision": ("c128" if prec == B.PREC_C128
                          else "c64 sweep + FP32 correction polish (FP64 accuracy)"),
            "bounds": [round(a, 4), round(b, 4), bounds], "window": [-d, d], "n_s": w["n_s"],
-           "n_p": n_p, "time_to_solution_s": round(T, 3), "status": int(rc),
+           "n_p": n_p, "time_to_solution_s": round(T, 3), "matrix_build_s": round(t_build, 3),
+           "status": int(rc),
            "eigenpairs_found": int(ev.size), "max_residual": float(rs.max()) if rs.size else None,
            "iterations": stats["iterations"], "iterations_c64": stats["iterations_c64"],
            "iterations_correction": stats["iterations_corr"],
