@@ -139,7 +139,8 @@ def test_filter_c64_vs_reference(env, orc, storage, n_s):
 
 
 @pytest.mark.parametrize("storage", ["sell", "stencil"])
-def test_filter_columns_vs_reference(env, orc, storage):
+@pytest.mark.parametrize("n_p", [60, 2])
+def test_filter_columns_vs_reference(env, orc, storage, n_p):
     """chebfd_filter_apply_columns (complex64): every column filtered with a
     coefficient sequence of its own (here the window expansion of a window
     shifted per column) equals the reference's filter of that column alone;
@@ -151,7 +152,7 @@ def test_filter_columns_vs_reference(env, orc, storage):
     a, b = orc.gershgorin(Hr)
     st = B.STORAGE_SELL if storage == "sell" else B.STORAGE_STENCIL
     H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=4, storage=st)
-    n_s, n_p, ldg = 34, 60, 37
+    n_s, ldg = 34, 37
     X = inp.random_block(Hr.n, n_s, seed=8).astype(np.complex64).astype(np.complex128)
     G = np.zeros((n_p + 1, ldg))
     ref = np.empty_like(X)
@@ -707,6 +708,27 @@ def test_precision_sweep_vs_golden(env, orc, seed):
     print(f"seed {seed}: sweep eigenvalue error {err32:.2e} S_w, sweep residuals "
           f"{stats['sweep_residuals'].min():.1e}..{stats['sweep_residuals'].max():.1e}, "
           f"{stats['iterations_corr']} correction passes")
+
+
+def test_precision_form_small_matrix_polishes_in_fp64(env, orc):
+    """A matrix of 64 rows with degree 300: the correction pass's
+    coefficient table ((n_p + 1) x N_S doubles) does not fit the complex128
+    block it borrows, so the polish runs FP64 filter passes; the dense
+    spectrum is found as before."""
+    torch, B, ctx = env
+    L = (2, 2, 4)
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=2)
+    w, d = _dense_window(orc, Hr, 4)
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=2)
+    p = B.default_params(lam_lo=-d, lam_hi=d, n_s=16, n_p=300, eps=1e-9, seed=5,
+                         precision=B.PREC_C64, max_iter=100)
+    rc, ev, rs, V, stats = B.chebfd_solve(ctx, H, p)
+    S_w = max(abs(stats["a"]), abs(stats["b"]))
+    want = w[np.abs(w) <= d]
+    assert rc == 0 and ev.size == want.size == 4, (rc, ev, want)
+    assert np.abs(ev - want).max() < 1e-10 * S_w and rs.max() <= 1e-9
+    assert stats["iterations_corr"] == 0
+    assert B.PREC_C128 in [h["precision"] for h in stats["history"]]
 
 
 def test_precision_polish_forms_agree(env, orc):
