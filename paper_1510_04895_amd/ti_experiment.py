@@ -19,8 +19,8 @@ N_MVM = N_p x N_S x iterations.
            fig:ConvTopi (smallest in-window residual, largest accepted one,
            against N_MVM).
 
-The disorder realisation is this build's (seed 1), so N_T differs from the
-paper's 144; the KPM estimate of Eq. DOS:target (2048 moments of 16
+The disorder realisation here is seed 1 of the generator, so N_T differs
+from the paper's 144; the KPM estimate of Eq. DOS:target (2048 moments of 16
 random-phase vectors) is reported beside the converged count, and the
 linear-DOS effort estimate of Eq. (etanlinear) -- eta_opt(delta') N_S
 (-log10 eps) with delta' = delta (sqrt(N_S/N_T) - 1), minimised over N_S --
