@@ -245,6 +245,10 @@ def main():
     ap.add_argument("--order", type=int, default=-1, choices=[-1, 0, 1],
                     help="block order of the matrix-free step (tuning key 'order'): -1 "
                          "automatic, 0 column-slab major, 1 tiled lattice order")
+    ap.add_argument("--lanes", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="lanes per row or site (tuning key 'lanes'; 0 = automatic)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="strip width of the tiled lattice order (tuning key 'tile'; -1 = default)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the bandwidth probe and the timed fused launches (no solves)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,6 +271,10 @@ def main():
     ctx = B.Context(0)
     if args.order != -1:
         B.chebfd_set_tuning(ctx, "order", args.order)
+    if args.lanes:
+        B.chebfd_set_tuning(ctx, "lanes", args.lanes)
+    if args.tile != -1:
+        B.chebfd_set_tuning(ctx, "tile", args.tile)
     prec = B.PREC_C128 if args.precision == "c128" else B.PREC_C64
 
     # attainable bandwidth (read-only reduction, copy, 3-read/2-write stream)
@@ -328,7 +336,9 @@ def main():
     mats.clear()
     torch.cuda.empty_cache()
 
-    traffic = measured_traffic(args.storage, args.precision, args.workload)
+    # the committed counters were taken in the default launch shape
+    default_shape = args.order == -1 and not args.lanes and args.tile == -1
+    traffic = measured_traffic(args.storage, args.precision, args.workload) if default_shape else None
     t_step = headline["t_step"]
     roof = {"bound": "hbm", "achieved": round(headline["vstep"] / t_step / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -339,7 +349,8 @@ def main():
             "avg_launch_us": round(t_step * 1e6, 2),
             "frac_of_probe_3r2w": round(headline["vstep"] / t_step / 1e9 / probe[2], 4)}
     cfg = {"workload": args.workload, "lattice": "x".join(map(str, L)), "N": n, "nnz": nnz,
-           "n_s": n_s, "storage": args.storage, "order": args.order,
+           "n_s": n_s, "storage": args.storage, "order": args.order, "lanes": args.lanes,
+           "tile": args.tile,
            "sell_C_sigma": [w.get("sell_C", 32), w.get("sell_sigma", 256)]
            if args.storage == "sell" else None,
            "step": "one fused Chebyshev launch (spMMV + recurrence + accumulation)",

@@ -3,8 +3,9 @@
     python -m paper_1510_04895_amd.profile_summary stats KERNEL_STATS_CSV NAME "COMMAND"
         -> profiles/NAME.md: per-kernel calls / average / total / share.
     python -m paper_1510_04895_amd.profile_summary traffic STORAGE PREC WORKLOAD \\
-           FETCH_DIR WRITE_DIR "FETCH_COMMAND" "WRITE_COMMAND"
-        -> profiles/traffic_STORAGE_PREC_WORKLOAD.json: HBM bytes per fused
+           FETCH_DIR WRITE_DIR "FETCH_COMMAND" "WRITE_COMMAND" [NAME]
+        -> profiles/traffic_STORAGE_PREC_WORKLOAD.json (or NAME.json for another
+           launch shape): HBM bytes per fused
            MODE_STEP launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
            each scaled by what the same counter reads for the plain copy
            kernel of the bandwidth probe (2 GiB read + 2 GiB written), with
@@ -55,7 +56,7 @@ def _csv_in(d):
     raise FileNotFoundError(d)
 
 
-def traffic(storage, prec, workload, fdir, wdir, cmd_f, cmd_w):
+def traffic(storage, prec, workload, fdir, wdir, cmd_f, cmd_w, name=None):
     sys.path.insert(0, ROOT)
     import bench
     F, Wc = _pmc(_csv_in(fdir)), _pmc(_csv_in(wdir))
@@ -71,7 +72,10 @@ def traffic(storage, prec, workload, fdir, wdir, cmd_f, cmd_w):
                write_bytes=sum(ws) / len(ws) * 1024 * w_scale, fetch_scale=f_scale,
                write_scale=w_scale, kernel_source_sha=bench.source_sha(storage),
                commands=[cmd_f, cmd_w])
-    path = os.path.join(ROOT, "profiles", f"traffic_{storage}_{prec}_{workload}.json")
+    # the default name is the record bench.py reads (default launch shape);
+    # counters of another launch shape take a name of their own
+    name = name or f"traffic_{storage}_{prec}_{workload}"
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
@@ -138,7 +142,7 @@ if __name__ == "__main__":
     if what == "stats":
         print(stats(*sys.argv[2:5]))
     elif what == "traffic":
-        print(json.dumps(traffic(*sys.argv[2:9]), indent=1))
+        print(json.dumps(traffic(*sys.argv[2:10]), indent=1))
     elif what == "mfma":
         print(json.dumps(mfma(*sys.argv[2:5]), indent=1))
     else:
