@@ -242,3 +242,21 @@ def test_dos_params_match_oracle_density(B, orc):
         mref = orc.dos_margin(mu, H.n, a, b, -d, d, 120)
         # the library floors the margin at the kernel width 2 S_w / M
         assert abs(mg - max(mref, (b - a) / 256)) <= 1e-9 * (b - a), (d, mg, mref)
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/chebfd.h is a C interface: it compiles as pedantic C99 with
+    every warning an error, and a C caller can fill the parameter block."""
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "chebfd.h"\n'
+                   "int main(void) {\n"
+                   "    chebfd_params p;\n"
+                   "    chebfd_stats s;\n"
+                   "    chebfd_iter_info h;\n"
+                   "    (void)s; (void)h;\n"
+                   "    return chebfd_params_default(&p) == 0 ? p.polish : 1;\n"
+                   "}\n")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I" + os.path.join(ROOT, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "use_header.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
