@@ -186,7 +186,7 @@ def step_time(torch, B, ctx, H, blocks, a, b, k):
     return (tk - t2[1]) / (k - 2)
 
 
-def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
+def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag, polish=None):
     """One complete solve (Sec. 3.1 steps 1-8) on a lattice with its window
     from the workload table; returns a summary dict and the eigenvalues."""
     w = inp.WORKLOADS[wname]
@@ -206,7 +206,8 @@ def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
     n_p, eta = B.chebfd_optimal_np(a, b, -d, d, -d - dp, d + dp)
     p = B.default_params(lam_lo=-d, lam_hi=d, n_s=w["n_s"], n_p=n_p, kernel=w["kernel"],
                          mu=w["mu"], eps=w["eps"], max_iter=60, precision=prec, lock=1,
-                         seed=w["seeds"][0], vectors=0, bounds=steps)
+                         seed=w["seeds"][0], vectors=0, bounds=steps,
+                         polish=B.POLISH_CORRECTION if polish is None else polish)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, ev, rs, _, stats = B.chebfd_solve(ctx, H, p)
@@ -216,6 +217,7 @@ def solve_case(torch, B, ctx, wname, storage, prec, bounds, tag):
     torch.cuda.empty_cache()
     out = {"workload": wname, "storage": storage,
            "precision": ("c128" if prec == B.PREC_C128
+                         else "c64 sweep + FP64 filter polish" if polish == B.POLISH_FP64
                          else "c64 sweep + FP32 correction polish (FP64 accuracy)"),
            "bounds": [round(a, 4), round(b, 4), bounds], "window": [-d, d], "n_s": w["n_s"],
            "n_p": n_p, "time_to_solution_s": round(T, 3), "matrix_build_s": round(t_build, 3),
@@ -373,8 +375,10 @@ def main():
                              "flop_convention": "same complex counting (Sec. 4.2)"}}
 
     if not args.kernel_only:
-        # time to all window eigenpairs: the precision form against the FP64
-        # form at 128x128x64 (Lanczos bounds), and the FP64 solve at 64x64x32
+        # time to all window eigenpairs: the precision form (with FP32
+        # correction passes, and with FP64 passes in the polish) against the
+        # FP64 form at 128x128x64 (Lanczos bounds), the FP64 solve at
+        # 64x64x32 and at 8x8x8
         tts = {}
         r64, ev64 = solve_case(torch, B, ctx, "ti_128x128x64", args.storage, B.PREC_C128,
                                "lanczos", "128x128x64 c128")
@@ -387,6 +391,14 @@ def main():
         r32["speedup_over_fp64"] = round(r64["time_to_solution_s"] / r32["time_to_solution_s"], 3)
         tts["ti_128x128x64_fp64"] = r64
         tts["ti_128x128x64_precision_form"] = r32
+        # the same precision form with FP64 filter passes in the polish
+        rp, evp = solve_case(torch, B, ctx, "ti_128x128x64", args.storage, B.PREC_C64,
+                             "lanczos", "128x128x64 c64, FP64 polish", polish=B.POLISH_FP64)
+        rp["same_eigenvalues_as_fp64"] = bool(
+            evp.size == ev64.size and (ev64.size == 0 or
+                                       np.abs(evp - ev64).max() < 1e-10 * S_w))
+        rp["speedup_over_fp64"] = round(r64["time_to_solution_s"] / rp["time_to_solution_s"], 3)
+        tts["ti_128x128x64_precision_form_fp64_polish"] = rp
         r2, ev2 = solve_case(torch, B, ctx, "ti_64x64x32", args.storage, B.PREC_C128,
                              "gershgorin", "64x64x32 c128")
         gold = os.path.join(ROOT, "tests", "golden", "ti_64x64x32_V1_seed1_window0.23.txt")
