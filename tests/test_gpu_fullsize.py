@@ -227,3 +227,56 @@ def test_random_block_and_convert_beyond_2_32_elements(env, orc):
     finally:
         del X, Y
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_filter_sampled_rows_at_256x256x64(orc, prec):
+    """The largest lattice in the benchmark's launch configuration
+    (matrix-free, tiled lattice order with its XCD placement, 128 columns;
+    32 lanes per site in complex128, a whole wave per site in complex64):
+    a degree-3 filter, all of whose steps are fused launches, equals the
+    reference at sampled rows.  Those include the lattice corners, the
+    open z faces, the periodic wraps and the strip boundaries of the
+    tiled order.  The reference evaluates the filter there from its own
+    sparse rows and the input rows within three hops."""
+    import torch
+    from paper_1510_04895_amd import binding as B
+    from sampled import sampled_filter
+    torch.cuda.empty_cache()
+    L, n_s, seed = (256, 256, 64), 128, 31
+    Hr = orc.ti_hamiltonian(*L, pbc=3, V=1.0, seed=1)
+    a, b = orc.gershgorin(Hr)
+    gam = inp.random_gamma(3, seed=6)
+    ctx = B.Context(0)
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1, storage=B.STORAGE_STENCIL)
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    X = torch.empty((Hr.n, n_s), dtype=dt, device="cuda")
+    B.chebfd_random_block(ctx, X, seed=seed)
+    U, W = torch.empty_like(X), torch.empty_like(X)
+    B.chebfd_filter_apply(ctx, H, gam, a, b, X, U, W)
+    torch.cuda.synchronize()
+    del U, W
+    # sites: corners, open z faces, wraps, strip boundaries (x = 3, 4, 7,
+    # 8, 251, 252), and seeded random ones
+    Lx, Ly, Lz = L
+    pick = [(0, 0, 0), (Lx - 1, Ly - 1, Lz - 1), (3, 0, 1), (4, Ly - 1, 62), (7, 128, 0),
+            (8, 128, Lz - 1), (251, 5, 31), (252, 250, 32), (Lx - 1, 0, 33), (0, Ly - 1, 2)]
+    g = np.random.default_rng(7)
+    pick += [tuple(int(v) for v in g.integers(0, [Lx, Ly, Lz])) for _ in range(40)]
+    sites = [x + Lx * (y + Ly * z) for x, y, z in pick]
+    rows = [4 * s + o for s in sites for o in range(4)]
+
+    def xrows(idx):
+        # the input block: the reference generator's rows (rounded to
+        # complex64 as the library's complex64 block holds them)
+        out = np.concatenate([orc.random_block(1, n_s, seed=seed, stream=1, offset=int(r) * n_s)
+                              for r in idx])
+        return out.astype(np.complex64).astype(np.complex128) if prec == "c64" else out
+
+    got_rows, ref = sampled_filter(Hr, a, b, gam, rows, xrows)
+    got = X[torch.as_tensor(got_rows, device="cuda")].cpu().numpy().astype(np.complex128)
+    del X
+    torch.cuda.empty_cache()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    tol = 1e-12 * 3 if prec == "c128" else 30 * math.sqrt(3) * 2.0 ** -24
+    assert err < tol, err

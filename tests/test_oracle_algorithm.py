@@ -280,3 +280,19 @@ def test_solve_ti_4x4x4_harmonic_vs_dense(orc):
     a, b = stats["a"], stats["b"]
     assert np.abs(ev - want).max() < 1e-10 * max(abs(a), abs(b))
     assert np.linalg.norm(H.dense() @ V - V * ev, axis=0).max() <= 1e-9
+
+
+def test_sampled_filter_equals_reference_filter(orc):
+    """The sampled-row evaluation used by the full-size parity tests agrees
+    with the reference's filter of the whole block on a small lattice,
+    including open-boundary and periodic-wrap sites."""
+    import chebfd_inputs as inp
+    from sampled import sampled_filter
+    Hr = orc.ti_hamiltonian(6, 5, 4, pbc=3, V=1.0, seed=3)
+    a, b = orc.gershgorin(Hr)
+    X = inp.random_block(Hr.n, 5, seed=4)
+    gam = inp.random_gamma(3, seed=5)
+    full = orc.filter_block(Hr, a, b, gam, X)
+    rows = [0, 1, 3, 17, 55, Hr.n - 1, Hr.n - 4, 4 * 29 + 2]
+    got_rows, got = sampled_filter(Hr, a, b, gam, rows, lambda idx: X[idx])
+    assert np.abs(got - full[got_rows]).max() < 1e-13 * np.abs(full).max()
