@@ -229,11 +229,13 @@ def test_random_block_and_convert_beyond_2_32_elements(env, orc):
         torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_filter_sampled_rows_at_256x256x64(orc, prec):
-    """The largest lattice in the benchmark's launch configuration
-    (matrix-free, tiled lattice order with its XCD placement, 128 columns;
-    32 lanes per site in complex128, a whole wave per site in complex64):
+@pytest.mark.parametrize("storage,prec", [("stencil", "c128"), ("stencil", "c64"),
+                                          ("sell", "c128")])
+def test_filter_sampled_rows_at_256x256x64(orc, storage, prec):
+    """The largest lattice in the benchmark's launch configurations
+    (matrix-free: tiled lattice order with its XCD placement, 32 lanes per
+    site in complex128, a whole wave per site in complex64; SELL-32-256:
+    row groups of 4 in the tiled row order; 128 columns):
     a degree-3 filter, all of whose steps are fused launches, equals the
     reference at sampled rows.  Those include the lattice corners, the
     open z faces, the periodic wraps and the strip boundaries of the
@@ -248,7 +250,8 @@ def test_filter_sampled_rows_at_256x256x64(orc, prec):
     a, b = orc.gershgorin(Hr)
     gam = inp.random_gamma(3, seed=6)
     ctx = B.Context(0)
-    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1, storage=B.STORAGE_STENCIL)
+    H = B.Matrix.ti(ctx, L, pbc=3, V=1.0, seed=1,
+                    storage=B.STORAGE_STENCIL if storage == "stencil" else B.STORAGE_SELL)
     dt = torch.complex128 if prec == "c128" else torch.complex64
     X = torch.empty((Hr.n, n_s), dtype=dt, device="cuda")
     B.chebfd_random_block(ctx, X, seed=seed)
@@ -275,7 +278,7 @@ def test_filter_sampled_rows_at_256x256x64(orc, prec):
 
     got_rows, ref = sampled_filter(Hr, a, b, gam, rows, xrows)
     got = X[torch.as_tensor(got_rows, device="cuda")].cpu().numpy().astype(np.complex128)
-    del X
+    del X, H
     torch.cuda.empty_cache()
     err = np.abs(got - ref).max() / np.abs(ref).max()
     tol = 1e-12 * 3 if prec == "c128" else 30 * math.sqrt(3) * 2.0 ** -24
